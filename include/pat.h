@@ -1,0 +1,148 @@
+/*
+ * pat.h — C ABI of the MI355X (gfx950) photoacoustic forward / adjoint library.
+ *
+ * The library evaluates, for K initial-pressure datasets that share one sound
+ * speed, the forward map of eq. (2) (a k-space pseudospectral solution of the
+ * lossless wave problem, eq. (1), sampled at point sensors), the data misfit of
+ * eq. (4), the exact gradient of that misfit with respect to every p0_i and c
+ * (eqs. (5)-(9), as the gradient of the discrete objective), and the vector
+ * pieces of the projected L-BFGS reconstruction (eq. (10), eq. (11), Alg. 1)
+ * and of the multigrid continuation (Sec. 3.1, Sec. 4.1.2).
+ *
+ * Conventions (all entry points):
+ *  - Array arguments are DEVICE pointers unless marked "host".  The caller owns
+ *    every array; the library never frees caller memory.
+ *  - Fields are float32, row-major [ny][nx] (x fastest); K fields are stacked
+ *    [K][ny][nx]; sensor traces are [K][nt][m].
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *    default stream) and is asynchronous; results are valid once the stream has
+ *    reached that point.  Results are deterministic: the same inputs give the
+ *    same bits (no floating-point atomics).
+ *  - Every call returns a status: PAT_OK (0) or a negative PAT_E* code; a
+ *    failing call enqueues nothing.  pat_status_string() names a code.
+ *  - A plan and its internal scratch belong to one stream at a time: calls on
+ *    one plan that overlap on different streams race.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PAT_OK            0
+#define PAT_EINVAL       -1  /* null pointer, non-positive or inconsistent size   */
+#define PAT_EUNSUPPORTED -2  /* grid length without a compiled FFT plan, K > 64   */
+#define PAT_EWORKSPACE   -3  /* workspace too small, or not filled by pat_forward */
+#define PAT_EHIP         -4  /* HIP runtime error (launch or allocation)          */
+
+/* One computational grid.  nx, ny include the PML.  The time axis holds nt
+ * samples t_n = n*dt, n = 0..nt-1 (nt-1 updates).  c_ref is the fixed speed of
+ * the k-space correction kappa = sinc(c_ref |k| dt / 2); rho0 the constant
+ * ambient density; pml_alpha the PML absorption at its outer edge in nepers per
+ * grid point, profile alpha(d) = pml_alpha * (c_ref/dx) * (d/pml)^4 over the
+ * `pml` outermost points of every side.  Pixel i of an axis of length n sits at
+ * (i + 1/2 - n/2) * dx. */
+typedef struct pat_grid {
+  int32_t nx, ny;
+  int32_t nt;
+  int32_t pml;
+  double dx;
+  double dt;
+  double c_ref;
+  double rho0;
+  double pml_alpha;
+} pat_grid;
+
+typedef struct pat_plan pat_plan;
+
+/* Create a plan for K datasets on grid `g` with m point sensors at physical
+ * positions `sensor_xy` (HOST, [m][2] metres, (x, y), origin at the grid
+ * centre).  Sec. 2.2: the pressure at a sensor is the bilinear interpolation
+ * of its four surrounding pixels; the adjoint injects with the transpose.
+ * Supported axis lengths: 32 36 40 48 64 81 84 96 125 128 160 175 192 243 256
+ * 375 384 512 (products of 2, 3, 5, 7 with a compiled radix plan).
+ * Errors: PAT_EINVAL (sizes, sensor outside the interpolation range),
+ * PAT_EUNSUPPORTED (axis length, K > 64), PAT_EHIP (table upload).
+ * The plan owns small device tables (twiddles, PML profiles, sensor taps,
+ * kappa); release it with pat_plan_destroy. */
+int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* sensor_xy,
+                    pat_plan** plan);
+int pat_plan_destroy(pat_plan* plan);
+
+/* Workspace bytes for pat_forward / pat_adjoint_gradient.  ckpt_every = 0
+ * stores the whole pressure history (nt fields of K*ny*nx floats);
+ * ckpt_every = s > 0 stores the solver state every s steps and recomputes
+ * s-step segments during the adjoint (gradients are bit-identical either way). */
+int pat_workspace_size(const pat_plan* plan, int32_t ckpt_every, size_t* bytes);
+
+/* Forward map f of eq. (2) for all K datasets: data[k][n][:] = S p_k^n.
+ * c [ny][nx] (> 0), p0 [K][ny][nx], data [K][nt][m].
+ * record != 0 keeps what pat_adjoint_gradient needs in `ws` (the pressure
+ * history or the checkpoints, per ckpt_every); record == 0 (line-search
+ * trials) only needs the state part of the workspace and leaves the recorded
+ * part untouched.  ws must hold pat_workspace_size(plan, ckpt_every) bytes. */
+int pat_forward(pat_plan* plan, const float* c, const float* p0, float* data,
+                void* ws, size_t ws_bytes, int32_t ckpt_every, int32_t record, void* stream);
+
+/* Data term of eq. (4) with W_i = w[i] (w: DEVICE array of K weights 1/sigma_i):
+ * resid = w^2 (data - y) (the adjoint source, eq. (6) with the sign folded
+ * in) and J = 1/2 sum w^2 (data - y)^2 accumulated in float64 into the DEVICE
+ * scalar *J.  data, y, resid: [K][nt][m]; resid may alias data. */
+int pat_misfit(pat_plan* plan, const float* data, const float* y, const float* w,
+               float* resid, double* J, void* stream);
+
+/* Exact gradient of J with respect to every p0_k and the shared c (eqs. (5)-(9)
+ * for the discrete forward map): the adjoint field is driven backwards in time
+ * by `resid` [K][nt][m] (dJ/d data) injected at the sensors.
+ * g_p0 [K][ny][nx]; g_c [ny][nx] = sum over the K datasets (eq. (8)).
+ * Requires that the last pat_forward on this plan ran with record != 0 on the
+ * same ws, c and p0 (else PAT_EWORKSPACE). */
+int pat_adjoint_gradient(pat_plan* plan, const float* c, const float* p0, const float* resid,
+                         float* g_p0, float* g_c, void* ws, size_t ws_bytes, void* stream);
+
+/* Eq. (10)-(11): x <- P(x - alpha d), P the element-wise clamp to [L, U].
+ * Bounds per element (lo, hi DEVICE arrays of n) or, where an array pointer is
+ * NULL, the scalar lo_s / hi_s (hi_s = +INFINITY allowed: no upper bound).
+ * lo == hi pins an element. */
+int pat_project_update(int64_t n, float* x, const float* d, float alpha,
+                       const float* lo, const float* hi, float lo_s, float hi_s, void* stream);
+
+/* Sec. 3.1: bilinear interpolation of nchan coarse fields [nchan][nyc][nxc]
+ * onto a finer grid [nchan][nyf][nxf] covering the same physical square
+ * (cell-centred pixels), clamped at the border.  Each fine value is a convex
+ * combination of at most four coarse values. */
+int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc,
+                float* fine, int32_t nyf, int32_t nxf, void* stream);
+
+/* Sec. 4.1.2: linear interpolation in time of traces y [nlead][nt_src][m]
+ * sampled at n*dt_src onto out [nlead][nt_dst][m] at n*dt_dst (held at the
+ * last sample beyond the end). */
+int pat_time_interp(int32_t nlead, int32_t nt_src, int32_t m, const float* y, double dt_src,
+                    float* out, int32_t nt_dst, double dt_dst, void* stream);
+
+/* Alg. 1 (two-loop recursion): d = H g for the L-BFGS inverse Hessian built
+ * from `npairs` pairs s_j = x_{j+1} - x_j, y_j = g_{j+1} - g_j given oldest
+ * first (s, y: HOST arrays of npairs DEVICE pointers to n floats), with
+ * H^0 = (s^T y / y^T y) I of the newest pair.  Dot products accumulate in
+ * float64.  npairs = 0 gives d = g.  `scratch`: DEVICE buffer of at least
+ * pat_lbfgs_scratch_bytes(npairs) bytes.  d may alias g. */
+size_t pat_lbfgs_scratch_bytes(int32_t npairs);
+int pat_lbfgs_direction(int64_t n, const float* g, int32_t npairs, const float* const* s,
+                        const float* const* y, float* d, void* scratch, void* stream);
+
+/* Float64 dot product a . b of n floats into the DEVICE scalar *out
+ * (deterministic two-level reduction; `scratch` as for pat_lbfgs_direction
+ * with npairs = 0). */
+int pat_dot(int64_t n, const float* a, const float* b, double* out, void* scratch, void* stream);
+
+const char* pat_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAT_H */

@@ -1,0 +1,646 @@
+// pat_api.hip — C ABI (include/pat.h): plans, workspace layout and the time
+// loops of the forward solve and of its adjoint, on top of the fused passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pat.h"
+#include "vec_kernels.hpp"
+#include "wave_kernels.hpp"
+
+using namespace pat;
+
+namespace {
+
+constexpr int kSupported[] = {32, 36, 40, 48, 64, 81, 84, 96, 125, 128, 160, 175, 192, 243, 256, 375, 384, 512};
+
+bool supported(int n) {
+  for (int s : kSupported)
+    if (s == n) return true;
+  return false;
+}
+
+#define PAT_SIZE_CASES(X)                                                                                  \
+  X(32) X(36) X(40) X(48) X(64) X(81) X(84) X(96) X(125) X(128) X(160) X(175) X(192) X(243) X(256) X(375) \
+  X(384) X(512)
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int grid_blocks(int64_t n, int threads = 256) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b > 8192) b = 8192;
+  return (int)std::max<int64_t>(b, 1);
+}
+
+}  // namespace
+
+struct pat_plan {
+  pat_grid g;
+  int K = 0, m = 0, nh = 0;
+  void* dev = nullptr;       // one allocation for every table
+  Tables tb{};
+  double* red = nullptr;     // RED_BLOCKS partial sums (misfit)
+  // bookkeeping of the last recording forward (for pat_adjoint_gradient)
+  bool recorded = false;
+  const void* rec_ws = nullptr;
+  const float* rec_c = nullptr;
+  const float* rec_p0 = nullptr;
+  int rec_ckpt = 0;
+};
+
+namespace {
+
+struct Layout {
+  size_t F = 0, Sp = 0;           // bytes of one [K][ny][nx] field / one [K][ny][nh] spectrum
+  size_t ux, uy, rx, ry;          // forward state
+  size_t uhx, uhy, rhx, rhy, gck; // adjoint state
+  size_t SA, SB, SC, SD;          // spectra (forward pair, adjoint pair)
+  size_t dpart;                   // [K][nt][2][m]
+  size_t hist;                    // store-all history [nt] fields, or the segment buffer [s] fields
+  size_t ckpt;                    // checkpoints: ncks * (4 fields + 1 spectrum)
+  int ncks = 0, s = 0;
+  size_t total = 0;
+};
+
+Layout make_layout(const pat_plan* p, int ckpt_every) {
+  Layout L;
+  const pat_grid& g = p->g;
+  L.F = (size_t)p->K * g.ny * g.nx * sizeof(float);
+  L.Sp = (size_t)p->K * g.ny * p->nh * sizeof(float2);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += align256(b);
+    return o;
+  };
+  L.ux = take(L.F); L.uy = take(L.F); L.rx = take(L.F); L.ry = take(L.F);
+  L.uhx = take(L.F); L.uhy = take(L.F); L.rhx = take(L.F); L.rhy = take(L.F); L.gck = take(L.F);
+  L.SA = take(L.Sp); L.SB = take(L.Sp); L.SC = take(L.Sp); L.SD = take(L.Sp);
+  L.dpart = take((size_t)p->K * g.nt * 2 * p->m * sizeof(float));
+  L.s = ckpt_every;
+  if (ckpt_every <= 0) {
+    L.hist = take(L.F * (size_t)g.nt);
+    L.ckpt = off;
+    L.ncks = 0;
+  } else {
+    L.hist = take(L.F * (size_t)ckpt_every);
+    // checkpoints at n = s, 2s, ... < nt - 1
+    L.ncks = g.nt >= 2 ? (g.nt - 2) / ckpt_every : 0;
+    L.ckpt = take((4 * align256(L.F) + align256(L.Sp)) * (size_t)L.ncks);
+  }
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+int last_error() { return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP; }
+
+// ----------------------------------------------------------------------------
+// Launchers (template dispatch on the transform length)
+// ----------------------------------------------------------------------------
+template <int NX>
+int rows_blocks(const pat_plan* p) {
+  return p->K * ((p->g.ny + RowCfg<NX>::ROWS - 1) / RowCfg<NX>::ROWS);
+}
+template <int NY>
+int cols_blocks(const pat_plan* p) {
+  return p->K * ((p->nh + ColCfg<NY>::TC - 1) / ColCfg<NY>::TC);
+}
+
+int launch_fwd_init(const pat_plan* p, hipStream_t st, const float* c, const float* p0, float* rx, float* ry,
+                    float* hist0, float* dpart, float2* SA) {
+  switch (p->g.nx) {
+#define X(N)                                                                                           \
+  case N:                                                                                              \
+    hipLaunchKernelGGL(k_fwd_init<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, p0, rx, ry, \
+                       hist0, dpart, SA);                                                              \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return last_error();
+}
+
+int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2* SA, float2* SB, int first) {
+  switch (p->g.nx) {
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(k_fwd_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, ux, uy, SA, SB, first); \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return last_error();
+}
+
+int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx, float* ry, float* hist,
+                   float* dpart_n, float2* SA, float2* SB) {
+  switch (p->g.nx) {
+#define X(N)                                                                                               \
+  case N:                                                                                                  \
+    hipLaunchKernelGGL(k_fwd_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, rx, ry, hist, \
+                       dpart_n, SA, SB);                                                                   \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return last_error();
+}
+
+template <int MODE>
+int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float scale) {
+  switch (p->g.ny) {
+#define X(N)                                                                                                 \
+  case N:                                                                                                    \
+    hipLaunchKernelGGL((k_col<N, MODE>), dim3(cols_blocks<N>(p)), dim3(ColCfg<N>::BLOCK), 0, st, p->tb, SA, \
+                       SB, scale);                                                                           \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return last_error();
+}
+
+int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const float* p_n, const float* resid_n,
+                   float* rhx, float* rhy, float* gck, float2* SA, float2* SB) {
+  switch (p->g.nx) {
+#define X(N)                                                                                                \
+  case N:                                                                                                   \
+    hipLaunchKernelGGL(k_adj_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, p_n, resid_n, rhx, \
+                       rhy, gck, SA, SB);                                                                   \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return last_error();
+}
+
+int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, float2* SA, float2* SB, int final_) {
+  switch (p->g.nx) {
+#define X(N)                                                                                                     \
+  case N:                                                                                                        \
+    hipLaunchKernelGGL(k_adj_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, uhx, uhy, SA, SB, final_); \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return last_error();
+}
+
+int launch_adj_final(const pat_plan* p, hipStream_t st, const float* c, const float* p0, const float* resid0,
+                     const float* rhx, const float* rhy, float* gck, float* gp0, const float2* SA) {
+  switch (p->g.nx) {
+#define X(N)                                                                                               \
+  case N:                                                                                                  \
+    hipLaunchKernelGGL(k_adj_final<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, p0, resid0, \
+                       rhx, rhy, gck, gp0, SA);                                                            \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return last_error();
+}
+
+int fill_zero(hipStream_t st, void* ptr, size_t bytes) {
+  const int64_t n = (int64_t)(bytes / sizeof(float));
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_blocks(n)), dim3(256), 0, st, static_cast<float*>(ptr), n);
+  return last_error();
+}
+
+int copy_dev(hipStream_t st, const void* src, void* dst, size_t bytes) {
+  const int64_t n = (int64_t)(bytes / sizeof(float));
+  hipLaunchKernelGGL(k_copy, dim3(grid_blocks(n)), dim3(256), 0, st, n, static_cast<const float*>(src),
+                     static_cast<float*>(dst));
+  return last_error();
+}
+
+#define PAT_TRY(expr)          \
+  do {                         \
+    int _s = (expr);           \
+    if (_s != PAT_OK) return _s; \
+  } while (0)
+
+// One forward update n -> n+1 (four passes).
+int forward_step(const pat_plan* p, hipStream_t st, const float* c, float* ux, float* uy, float* rx, float* ry,
+                 float2* SA, float2* SB, int n, float* hist_next, float* dpart_next) {
+  const pat_grid& g = p->g;
+  const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
+  PAT_TRY(launch_col<COL_GRAD1>(p, st, SA, SB, (float)(g.dt / g.rho0 * nrm)));
+  PAT_TRY(launch_fwd_u(p, st, ux, uy, SA, SB, n == 0 ? 1 : 0));
+  PAT_TRY(launch_col<COL_PAIRM>(p, st, SA, SB, (float)(g.dt * g.rho0 * nrm)));
+  PAT_TRY(launch_fwd_rho(p, st, c, rx, ry, hist_next, dpart_next, SA, SB));
+  return PAT_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Host-side tables
+// ----------------------------------------------------------------------------
+double wavenumber(int i, int n, double d) {
+  const int mm = i < (n + 1) / 2 ? i : i - n;   // FFT order, Nyquist negative
+  return 2.0 * M_PI * mm / (n * d);
+}
+
+// k * (i exp(sgn i k d/2)); at the Nyquist bin of an even axis only the real part.
+float2 shift_factor(int i, int n, double d, int sgn) {
+  const double k = wavenumber(i, n, d);
+  const double th = k * d / 2.0;
+  double re = -sgn * k * std::sin(th);
+  double im = k * std::cos(th);
+  if (n % 2 == 0 && i == n / 2) im = 0.0;
+  return make_float2((float)re, (float)im);
+}
+
+double pml_depth(int n, int P, double x) {
+  double d = std::max(P - x, x - (n - 1 - P));
+  return d > 0.0 ? d : 0.0;
+}
+
+void pml_axis(const pat_grid& g, int n, std::vector<float>& a, std::vector<float>& as, std::vector<float>& a2,
+              std::vector<float>& as2, std::vector<float>& wf) {
+  a.resize(n); as.resize(n); a2.resize(n); as2.resize(n); wf.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double fa = 1.0, fs = 1.0;
+    if (g.pml > 0) {
+      const double d0 = pml_depth(n, g.pml, (double)i) / g.pml;
+      const double d1 = pml_depth(n, g.pml, i + 0.5) / g.pml;
+      const double amax = g.pml_alpha * g.c_ref / g.dx;
+      fa = std::exp(-amax * d0 * d0 * d0 * d0 * g.dt / 2.0);
+      fs = std::exp(-amax * d1 * d1 * d1 * d1 * g.dt / 2.0);
+    }
+    a[i] = (float)fa;
+    as[i] = (float)fs;
+    a2[i] = (float)(fa * fa);
+    as2[i] = (float)(fs * fs);
+    wf[i] = (float)(fs - 0.5 * fs * fs);
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* pat_status_string(int s) {
+  switch (s) {
+    case PAT_OK: return "ok";
+    case PAT_EINVAL: return "invalid argument";
+    case PAT_EUNSUPPORTED: return "unsupported size";
+    case PAT_EWORKSPACE: return "workspace too small or not filled by a recording pat_forward";
+    case PAT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* sensor_xy, pat_plan** out) {
+  if (!g || !out || !sensor_xy) return PAT_EINVAL;
+  *out = nullptr;
+  if (g->nx <= 0 || g->ny <= 0 || g->nt <= 0 || K <= 0 || m <= 0 || g->pml < 0 || !(g->dx > 0) ||
+      !(g->dt > 0) || !(g->c_ref > 0) || !(g->rho0 > 0) || !(g->pml_alpha >= 0))
+    return PAT_EINVAL;
+  if (2 * g->pml >= g->nx || 2 * g->pml >= g->ny) return PAT_EINVAL;
+  if (!supported(g->nx) || !supported(g->ny) || K > 64) return PAT_EUNSUPPORTED;
+  const int nx = g->nx, ny = g->ny, nh = nx / 2 + 1;
+
+  // --- sensors: bilinear taps on cell centres (Sec. 2.2)
+  std::vector<GatherEnt> gent;
+  struct Tap { int row, ix, sensor; float w; };
+  std::vector<Tap> taps;
+  for (int s = 0; s < m; ++s) {
+    const double fx = sensor_xy[2 * s] / g->dx + nx / 2.0 - 0.5;
+    const double fy = sensor_xy[2 * s + 1] / g->dx + ny / 2.0 - 0.5;
+    if (!std::isfinite(fx) || !std::isfinite(fy)) return PAT_EINVAL;
+    const int i0 = (int)std::floor(fx), j0 = (int)std::floor(fy);
+    if (i0 < 0 || j0 < 0 || i0 + 1 > nx - 1 || j0 + 1 > ny - 1) return PAT_EINVAL;
+    const double tx = fx - i0, ty = fy - j0;
+    gent.push_back({j0, i0, s, 0, (float)((1 - tx) * (1 - ty)), (float)(tx * (1 - ty))});
+    gent.push_back({j0 + 1, i0, s, 1, (float)((1 - tx) * ty), (float)(tx * ty)});
+    taps.push_back({j0, i0, s, (float)((1 - tx) * (1 - ty))});
+    taps.push_back({j0, i0 + 1, s, (float)(tx * (1 - ty))});
+    taps.push_back({j0 + 1, i0, s, (float)((1 - tx) * ty)});
+    taps.push_back({j0 + 1, i0 + 1, s, (float)(tx * ty)});
+  }
+  std::stable_sort(gent.begin(), gent.end(), [](const GatherEnt& a, const GatherEnt& b) { return a.row < b.row; });
+  std::vector<int32_t> grs(ny + 1, 0);
+  for (const auto& e : gent) grs[e.row + 1]++;
+  for (int y = 0; y < ny; ++y) grs[y + 1] += grs[y];
+  std::stable_sort(taps.begin(), taps.end(), [](const Tap& a, const Tap& b) {
+    return a.row != b.row ? a.row < b.row : a.ix < b.ix;
+  });
+  std::vector<ScatterPix> spix;
+  std::vector<ScatterTap> stap;
+  for (size_t i = 0; i < taps.size();) {
+    size_t j = i;
+    ScatterPix px{taps[i].row, taps[i].ix, (int32_t)stap.size(), 0};
+    while (j < taps.size() && taps[j].row == taps[i].row && taps[j].ix == taps[i].ix) {
+      stap.push_back({taps[j].sensor, taps[j].w});
+      ++j;
+    }
+    px.count = (int32_t)(j - i);
+    spix.push_back(px);
+    i = j;
+  }
+  std::vector<int32_t> srs(ny + 1, 0);
+  for (const auto& e : spix) srs[e.row + 1]++;
+  for (int y = 0; y < ny; ++y) srs[y + 1] += srs[y];
+
+  // --- FFT twiddles, staggered derivative factors, kappa, PML
+  std::vector<float2> twx(nx), twy(ny), exp_(nh), exm(nh), eyp(ny), eym(ny);
+  for (int j = 0; j < nx; ++j) twx[j] = make_float2((float)std::cos(2 * M_PI * j / nx), (float)-std::sin(2 * M_PI * j / nx));
+  for (int j = 0; j < ny; ++j) twy[j] = make_float2((float)std::cos(2 * M_PI * j / ny), (float)-std::sin(2 * M_PI * j / ny));
+  for (int i = 0; i < nh; ++i) { exp_[i] = shift_factor(i, nx, g->dx, +1); exm[i] = shift_factor(i, nx, g->dx, -1); }
+  for (int i = 0; i < ny; ++i) { eyp[i] = shift_factor(i, ny, g->dx, +1); eym[i] = shift_factor(i, ny, g->dx, -1); }
+  std::vector<float> kap((size_t)ny * nh);
+  for (int e = 0; e < ny; ++e) {
+    const double ky = wavenumber(e, ny, g->dx);
+    for (int i = 0; i < nh; ++i) {
+      const double kx = wavenumber(i, nx, g->dx);
+      const double arg = g->c_ref * std::sqrt(kx * kx + ky * ky) * g->dt / 2.0;
+      kap[(size_t)e * nh + i] = (float)(arg == 0.0 ? 1.0 : std::sin(arg) / arg);
+    }
+  }
+  std::vector<float> ax, asx, ax2, asx2, wfx, ay, asy, ay2, asy2, wfy;
+  pml_axis(*g, nx, ax, asx, ax2, asx2, wfx);
+  pml_axis(*g, ny, ay, asy, ay2, asy2, wfy);
+
+  // --- one device blob
+  struct Piece { const void* src; size_t bytes; size_t off; };
+  std::vector<Piece> pieces;
+  size_t total = 0;
+  auto add = [&](const void* src, size_t bytes) {
+    pieces.push_back({src, bytes, total});
+    total += align256(std::max<size_t>(bytes, 4));
+    return pieces.size() - 1;
+  };
+  size_t i_twx = add(twx.data(), nx * sizeof(float2)), i_twy = add(twy.data(), ny * sizeof(float2));
+  size_t i_exp = add(exp_.data(), nh * sizeof(float2)), i_exm = add(exm.data(), nh * sizeof(float2));
+  size_t i_eyp = add(eyp.data(), ny * sizeof(float2)), i_eym = add(eym.data(), ny * sizeof(float2));
+  size_t i_kap = add(kap.data(), kap.size() * sizeof(float));
+  size_t i_ax = add(ax.data(), nx * 4), i_asx = add(asx.data(), nx * 4), i_ax2 = add(ax2.data(), nx * 4),
+         i_asx2 = add(asx2.data(), nx * 4), i_wfx = add(wfx.data(), nx * 4);
+  size_t i_ay = add(ay.data(), ny * 4), i_asy = add(asy.data(), ny * 4), i_ay2 = add(ay2.data(), ny * 4),
+         i_asy2 = add(asy2.data(), ny * 4), i_wfy = add(wfy.data(), ny * 4);
+  size_t i_grs = add(grs.data(), grs.size() * 4), i_gent = add(gent.data(), gent.size() * sizeof(GatherEnt));
+  size_t i_srs = add(srs.data(), srs.size() * 4), i_spix = add(spix.data(), spix.size() * sizeof(ScatterPix));
+  size_t i_stap = add(stap.data(), stap.size() * sizeof(ScatterTap));
+  size_t i_red = add(nullptr, RED_BLOCKS * sizeof(double));
+
+  pat_plan* p = new (std::nothrow) pat_plan();
+  if (!p) return PAT_EHIP;
+  p->g = *g;
+  p->K = K;
+  p->m = m;
+  p->nh = nh;
+  if (hipMalloc(&p->dev, total) != hipSuccess) {
+    delete p;
+    return PAT_EHIP;
+  }
+  std::vector<char> host(total, 0);
+  for (const auto& pc : pieces)
+    if (pc.src) std::memcpy(host.data() + pc.off, pc.src, pc.bytes);
+  if (hipMemcpy(p->dev, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->dev);
+    delete p;
+    return PAT_EHIP;
+  }
+  char* d = static_cast<char*>(p->dev);
+  auto P = [&](size_t i) { return static_cast<void*>(d + pieces[i].off); };
+  Tables& t = p->tb;
+  t.tw_x = (const float2*)P(i_twx); t.tw_y = (const float2*)P(i_twy);
+  t.ex_p = (const float2*)P(i_exp); t.ex_m = (const float2*)P(i_exm);
+  t.ey_p = (const float2*)P(i_eyp); t.ey_m = (const float2*)P(i_eym);
+  t.kappa = (const float*)P(i_kap);
+  t.ax = (const float*)P(i_ax); t.asx = (const float*)P(i_asx); t.ax2 = (const float*)P(i_ax2);
+  t.asx2 = (const float*)P(i_asx2); t.wfx = (const float*)P(i_wfx);
+  t.ay = (const float*)P(i_ay); t.asy = (const float*)P(i_asy); t.ay2 = (const float*)P(i_ay2);
+  t.asy2 = (const float*)P(i_asy2); t.wfy = (const float*)P(i_wfy);
+  t.g_row_start = (const int32_t*)P(i_grs); t.g_ent = (const GatherEnt*)P(i_gent);
+  t.s_row_start = (const int32_t*)P(i_srs); t.s_pix = (const ScatterPix*)P(i_spix);
+  t.s_tap = (const ScatterTap*)P(i_stap);
+  t.nx = nx; t.ny = ny; t.nh = nh; t.K = K; t.m = m; t.nt = g->nt;
+  p->red = (double*)P(i_red);
+  *out = p;
+  return PAT_OK;
+}
+
+int pat_plan_destroy(pat_plan* p) {
+  if (!p) return PAT_EINVAL;
+  if (p->dev) (void)hipFree(p->dev);
+  delete p;
+  return PAT_OK;
+}
+
+int pat_workspace_size(const pat_plan* p, int32_t ckpt_every, size_t* bytes) {
+  if (!p || !bytes || ckpt_every < 0) return PAT_EINVAL;
+  *bytes = make_layout(p, ckpt_every).total;
+  return PAT_OK;
+}
+
+int pat_forward(pat_plan* p, const float* c, const float* p0, float* data, void* ws, size_t ws_bytes,
+                int32_t ckpt_every, int32_t record, void* stream) {
+  if (!p || !c || !p0 || !data || !ws || ckpt_every < 0) return PAT_EINVAL;
+  const Layout L = make_layout(p, ckpt_every);
+  if (ws_bytes < L.total) return PAT_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const pat_grid& g = p->g;
+  float *ux = at<float>(ws, L.ux), *uy = at<float>(ws, L.uy), *rx = at<float>(ws, L.rx), *ry = at<float>(ws, L.ry);
+  float2 *SA = at<float2>(ws, L.SA), *SB = at<float2>(ws, L.SB);
+  float* dpart = at<float>(ws, L.dpart);
+  const size_t fl = L.F / sizeof(float);
+  const bool store_all = record && ckpt_every == 0;
+  float* hist = store_all ? at<float>(ws, L.hist) : nullptr;
+  if (record) p->recorded = false;
+
+  PAT_TRY(launch_fwd_init(p, st, c, p0, rx, ry, hist, dpart, SA));
+  for (int n = 0; n + 1 < g.nt; ++n) {
+    if (record && ckpt_every > 0 && n > 0 && n % ckpt_every == 0) {
+      const int slot = n / ckpt_every - 1;
+      char* ck = at<char>(ws, L.ckpt) + (size_t)slot * (4 * align256(L.F) + align256(L.Sp));
+      PAT_TRY(copy_dev(st, ux, ck, L.F));
+      PAT_TRY(copy_dev(st, uy, ck + align256(L.F), L.F));
+      PAT_TRY(copy_dev(st, rx, ck + 2 * align256(L.F), L.F));
+      PAT_TRY(copy_dev(st, ry, ck + 3 * align256(L.F), L.F));
+      PAT_TRY(copy_dev(st, SA, ck + 4 * align256(L.F), L.Sp));
+    }
+    PAT_TRY(forward_step(p, st, c, ux, uy, rx, ry, SA, SB, n, hist ? hist + (size_t)(n + 1) * fl : nullptr,
+                         dpart + (size_t)(n + 1) * 2 * p->m));
+  }
+  const int64_t rows = (int64_t)p->K * g.nt;
+  hipLaunchKernelGGL(k_sensor_finalize, dim3(grid_blocks(rows * p->m)), dim3(256), 0, st, dpart, data, rows, p->m);
+  PAT_TRY(last_error());
+  if (record) {
+    p->recorded = true;
+    p->rec_ws = ws;
+    p->rec_c = c;
+    p->rec_p0 = p0;
+    p->rec_ckpt = ckpt_every;
+  }
+  return PAT_OK;
+}
+
+int pat_misfit(pat_plan* p, const float* data, const float* y, const float* w, float* resid, double* J,
+               void* stream) {
+  if (!p || !data || !y || !w || !resid || !J) return PAT_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t per_k = (int64_t)p->g.nt * p->m;
+  hipLaunchKernelGGL(k_misfit, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, data, y, w, resid, p->red, per_k, p->K);
+  PAT_TRY(last_error());
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, st, p->red, RED_BLOCKS, J, 0.5);
+  return last_error();
+}
+
+int pat_adjoint_gradient(pat_plan* p, const float* c, const float* p0, const float* resid, float* g_p0, float* g_c,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !c || !p0 || !resid || !g_p0 || !g_c || !ws) return PAT_EINVAL;
+  if (!p->recorded || p->rec_ws != ws || p->rec_c != c || p->rec_p0 != p0) return PAT_EWORKSPACE;
+  const int s = p->rec_ckpt;
+  const Layout L = make_layout(p, s);
+  if (ws_bytes < L.total) return PAT_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const pat_grid& g = p->g;
+  const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
+  const size_t fl = L.F / sizeof(float);
+  float *uhx = at<float>(ws, L.uhx), *uhy = at<float>(ws, L.uhy), *rhx = at<float>(ws, L.rhx),
+        *rhy = at<float>(ws, L.rhy), *gck = at<float>(ws, L.gck);
+  float2 *SC = at<float2>(ws, L.SC), *SD = at<float2>(ws, L.SD);
+  float* hist = at<float>(ws, L.hist);
+  // adjoint state starts at zero (fill kernels: no memset nodes)
+  PAT_TRY(fill_zero(st, uhx, L.F));
+  PAT_TRY(fill_zero(st, uhy, L.F));
+  PAT_TRY(fill_zero(st, rhx, L.F));
+  PAT_TRY(fill_zero(st, rhy, L.F));
+  PAT_TRY(fill_zero(st, gck, L.F));
+  PAT_TRY(fill_zero(st, SC, L.Sp));
+  PAT_TRY(fill_zero(st, SD, L.Sp));
+
+  int seg0 = -1;   // checkpoint mode: the segment (n0, n0 + s] currently in the buffer
+  for (int n = g.nt - 1; n >= 1; --n) {
+    const float* p_n;
+    if (s == 0) {
+      p_n = hist + (size_t)n * fl;
+    } else {
+      const int n0 = ((n - 1) / s) * s;
+      if (n0 != seg0) {
+        // recompute p^{n0+1 .. n} from the checkpoint at n0 into the segment buffer
+        float *ux = at<float>(ws, L.ux), *uy = at<float>(ws, L.uy), *rx = at<float>(ws, L.rx),
+              *ry = at<float>(ws, L.ry);
+        float2 *SA = at<float2>(ws, L.SA), *SB = at<float2>(ws, L.SB);
+        if (n0 == 0) {
+          PAT_TRY(launch_fwd_init(p, st, c, p0, rx, ry, nullptr, nullptr, SA));
+        } else {
+          const int slot = n0 / s - 1;
+          const char* ck = at<char>(ws, L.ckpt) + (size_t)slot * (4 * align256(L.F) + align256(L.Sp));
+          PAT_TRY(copy_dev(st, ck, ux, L.F));
+          PAT_TRY(copy_dev(st, ck + align256(L.F), uy, L.F));
+          PAT_TRY(copy_dev(st, ck + 2 * align256(L.F), rx, L.F));
+          PAT_TRY(copy_dev(st, ck + 3 * align256(L.F), ry, L.F));
+          PAT_TRY(copy_dev(st, ck + 4 * align256(L.F), SA, L.Sp));
+        }
+        for (int j = n0; j < n; ++j)
+          PAT_TRY(forward_step(p, st, c, ux, uy, rx, ry, SA, SB, j, hist + (size_t)(j - n0) * fl, nullptr));
+        seg0 = n0;
+      }
+      p_n = hist + (size_t)(n - n0 - 1) * fl;
+    }
+    PAT_TRY(launch_col<COL_SUMM>(p, st, SC, SD, (float)(g.dt / g.rho0 * nrm)));
+    PAT_TRY(launch_adj_rho(p, st, c, p_n, resid + (size_t)n * p->m, rhx, rhy, gck, SC, SD));
+    PAT_TRY(launch_col<COL_PAIRP>(p, st, SC, SD, (float)(g.dt * g.rho0 * nrm)));
+    PAT_TRY(launch_adj_u(p, st, uhx, uhy, SC, SD, n == 1 ? 1 : 0));
+  }
+  PAT_TRY(launch_col<COL_SUMM>(p, st, SC, SD, (float)(g.dt / g.rho0 * nrm)));
+  PAT_TRY(launch_adj_final(p, st, c, p0, resid, rhx, rhy, gck, g_p0, SC));
+  const int64_t npix = (int64_t)g.ny * g.nx;
+  hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, gck, g_c, p->K, npix);
+  return last_error();
+}
+
+int pat_project_update(int64_t n, float* x, const float* d, float alpha, const float* lo, const float* hi,
+                       float lo_s, float hi_s, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !d))) return PAT_EINVAL;
+  if (n == 0) return PAT_OK;
+  hipLaunchKernelGGL(k_project_update, dim3(grid_blocks(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, x, d,
+                     alpha, lo, hi, lo_s, hi_s);
+  return last_error();
+}
+
+int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, float* fine, int32_t nyf, int32_t nxf,
+                void* stream) {
+  if (nchan <= 0 || nyc <= 0 || nxc <= 0 || nyf <= 0 || nxf <= 0 || !coarse || !fine) return PAT_EINVAL;
+  const int64_t n = (int64_t)nchan * nyf * nxf;
+  hipLaunchKernelGGL(k_prolong, dim3(grid_blocks(n)), dim3(256), 0, static_cast<hipStream_t>(stream), nchan, coarse,
+                     nyc, nxc, fine, nyf, nxf);
+  return last_error();
+}
+
+int pat_time_interp(int32_t nlead, int32_t nt_src, int32_t m, const float* y, double dt_src, float* out,
+                    int32_t nt_dst, double dt_dst, void* stream) {
+  if (nlead <= 0 || nt_src <= 0 || m <= 0 || nt_dst <= 0 || !y || !out || !(dt_src > 0) || !(dt_dst > 0))
+    return PAT_EINVAL;
+  const int64_t n = (int64_t)nlead * nt_dst * m;
+  hipLaunchKernelGGL(k_time_interp, dim3(grid_blocks(n)), dim3(256), 0, static_cast<hipStream_t>(stream), nlead,
+                     nt_src, m, y, dt_src, out, nt_dst, dt_dst);
+  return last_error();
+}
+
+size_t pat_lbfgs_scratch_bytes(int32_t npairs) {
+  return (size_t)(RED_BLOCKS + 2 * std::max(npairs, 0) + 2) * sizeof(double);
+}
+
+static int dot_into(hipStream_t st, int64_t n, const float* a, const float* b, double* partial, double* out) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, a, b, n, partial);
+  PAT_TRY(last_error());
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, out, 1.0);
+  return last_error();
+}
+
+int pat_dot(int64_t n, const float* a, const float* b, double* out, void* scratch, void* stream) {
+  if (n <= 0 || !a || !b || !out || !scratch) return PAT_EINVAL;
+  return dot_into(static_cast<hipStream_t>(stream), n, a, b, static_cast<double*>(scratch), out);
+}
+
+int pat_lbfgs_direction(int64_t n, const float* g, int32_t np, const float* const* s, const float* const* y, float* d,
+                        void* scratch, void* stream) {
+  if (n <= 0 || !g || !d || np < 0 || !scratch || (np > 0 && (!s || !y))) return PAT_EINVAL;
+  for (int j = 0; j < np; ++j)
+    if (!s[j] || !y[j]) return PAT_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* partial = static_cast<double*>(scratch);
+  double* sc = partial + RED_BLOCKS;
+  if (d != g) PAT_TRY(copy_dev(st, g, d, (size_t)n * sizeof(float)));
+  if (np == 0) return PAT_OK;
+  const int blocks = grid_blocks(n);
+  for (int j = 0; j < np; ++j) PAT_TRY(dot_into(st, n, y[j], s[j], partial, sc + j));
+  for (int j = np - 1; j >= 0; --j) {
+    PAT_TRY(dot_into(st, n, s[j], d, partial, sc + 2 * np));
+    hipLaunchKernelGGL(k_lbfgs_loop1, dim3(blocks), dim3(256), 0, st, n, d, y[j], sc, np, j);
+    PAT_TRY(last_error());
+  }
+  PAT_TRY(dot_into(st, n, y[np - 1], y[np - 1], partial, sc + 2 * np + 1));
+  hipLaunchKernelGGL(k_lbfgs_h0, dim3(blocks), dim3(256), 0, st, n, d, sc, np);
+  PAT_TRY(last_error());
+  for (int j = 0; j < np; ++j) {
+    PAT_TRY(dot_into(st, n, y[j], d, partial, sc + 2 * np));
+    hipLaunchKernelGGL(k_lbfgs_loop2, dim3(blocks), dim3(256), 0, st, n, d, s[j], sc, np, j);
+    PAT_TRY(last_error());
+  }
+  return PAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// vec_kernels.hpp — streaming vector kernels of the reconstruction (gfx950):
+// misfit and deterministic float64 reductions, bound projection, multigrid
+// prolongation, data time resampling, L-BFGS two-loop updates.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pat {
+
+constexpr int RED_BLOCKS = 512;   // first-level partial sums (fixed: deterministic)
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Sensor traces from the two per-row partials: data = part[.., 0, :] + part[.., 1, :]
+__global__ void k_sensor_finalize(const float* __restrict__ part, float* __restrict__ data, int64_t rows, int m) {
+  const int64_t n = rows * m;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / m, s = i % m;
+    data[i] = part[(r * 2) * m + s] + part[(r * 2 + 1) * m + s];
+  }
+}
+
+// g_c = sum_k gck[k]  (fixed order over k)
+__global__ void k_reduce_k(const float* __restrict__ gck, float* __restrict__ gc, int K, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < K; ++k) s += gck[(int64_t)k * n + i];
+    gc[i] = s;
+  }
+}
+
+__global__ void k_fill_zero(float* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.f;
+}
+
+// resid = w_k^2 (data - y); partial sums of w_k^2 (data - y)^2 in float64
+__global__ __launch_bounds__(RED_THREADS) void k_misfit(const float* __restrict__ data, const float* __restrict__ y,
+                                                        const float* __restrict__ w, float* __restrict__ resid,
+                                                        double* __restrict__ partial, int64_t per_k, int K) {
+  __shared__ double sh[RED_THREADS];
+  const int64_t n = per_k * K;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS) {
+    const float wk = w[i / per_k];
+    const float w2 = wk * wk;
+    const float d = data[i] - y[i];
+    resid[i] = w2 * d;
+    acc += (double)w2 * (double)d * (double)d;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out = factor * sum(partial[0..nb))
+__global__ __launch_bounds__(RED_THREADS) void k_sum_partials(const double* __restrict__ partial, int nb,
+                                                              double* __restrict__ out, double factor) {
+  __shared__ double sh[RED_THREADS];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += RED_THREADS) acc += partial[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = factor * s;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_dot_partial(const float* __restrict__ a, const float* __restrict__ b,
+                                                             int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[RED_THREADS];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS)
+    acc += (double)a[i] * (double)b[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// eq. (10)-(11): x <- clamp(x - alpha d, lo, hi)
+__global__ void k_project_update(int64_t n, float* __restrict__ x, const float* __restrict__ d, float alpha,
+                                 const float* __restrict__ lo, const float* __restrict__ hi, float lo_s, float hi_s) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float z = x[i] - alpha * d[i];
+    const float L = lo ? lo[i] : lo_s;
+    const float U = hi ? hi[i] : hi_s;
+    x[i] = z <= L ? L : (z >= U ? U : z);
+  }
+}
+
+// Bilinear, cell-centred, same physical extent, clamped at the border.
+__device__ __forceinline__ void axis_tap(int i, int nf, int nc, int& i0, int& i1, float& t) {
+  double f = (i + 0.5) * ((double)nc / (double)nf) - 0.5;
+  f = f < 0.0 ? 0.0 : (f > nc - 1.0 ? nc - 1.0 : f);
+  int a = (int)floor(f);
+  const int amax = nc >= 2 ? nc - 2 : 0;
+  a = a > amax ? amax : a;
+  i0 = a;
+  i1 = a + 1 < nc ? a + 1 : nc - 1;
+  t = (float)(f - a);
+}
+
+__global__ void k_prolong(int nchan, const float* __restrict__ coarse, int nyc, int nxc, float* __restrict__ fine,
+                          int nyf, int nxf) {
+  const int64_t n = (int64_t)nchan * nyf * nxf;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nxf);
+    const int y = (int)((i / nxf) % nyf);
+    const int64_t ch = i / ((int64_t)nxf * nyf);
+    int x0, x1, y0, y1;
+    float tx, ty;
+    axis_tap(x, nxf, nxc, x0, x1, tx);
+    axis_tap(y, nyf, nyc, y0, y1, ty);
+    const float* cc = coarse + ch * (int64_t)nyc * nxc;
+    const float r0 = cc[(int64_t)y0 * nxc + x0] * (1.f - tx) + cc[(int64_t)y0 * nxc + x1] * tx;
+    const float r1 = cc[(int64_t)y1 * nxc + x0] * (1.f - tx) + cc[(int64_t)y1 * nxc + x1] * tx;
+    fine[i] = r0 * (1.f - ty) + r1 * ty;
+  }
+}
+
+__global__ void k_time_interp(int nlead, int nt_src, int m, const float* __restrict__ y, double dt_src,
+                              float* __restrict__ out, int nt_dst, double dt_dst) {
+  const int64_t n = (int64_t)nlead * nt_dst * m;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(i % m);
+    const int t = (int)((i / m) % nt_dst);
+    const int64_t l = i / ((int64_t)m * nt_dst);
+    const double f = (t * dt_dst) / dt_src;
+    const float* yl = y + l * (int64_t)nt_src * m;
+    float v;
+    if (f >= nt_src - 1) {
+      v = yl[(int64_t)(nt_src - 1) * m + s];
+    } else {
+      const int a = (int)floor(f);
+      const float w = (float)(f - a);
+      v = yl[(int64_t)a * m + s] * (1.f - w) + yl[(int64_t)(a + 1) * m + s] * w;
+    }
+    out[i] = v;
+  }
+}
+
+__global__ void k_copy(int64_t n, const float* __restrict__ src, float* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Two-loop helpers; sc = device scalars: ys[j] at j, lambda[j] at np + j,
+// the latest dot at 2 np, y^T y at 2 np + 1.
+// first loop:  lambda_j = (s_j^T q) / (y_j^T s_j);  q -= lambda_j y_j
+__global__ void k_lbfgs_loop1(int64_t n, float* __restrict__ q, const float* __restrict__ yj, double* __restrict__ sc,
+                              int np, int j) {
+  const double lam = sc[2 * np] / sc[j];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[np + j] = lam;
+  const float fl = (float)lam;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    q[i] -= fl * yj[i];
+}
+
+// H^0 scaling: psi = (s^T y / y^T y) q  for the newest pair
+__global__ void k_lbfgs_h0(int64_t n, float* __restrict__ q, const double* __restrict__ sc, int np) {
+  const float g = (float)(sc[np - 1] / sc[2 * np + 1]);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    q[i] *= g;
+}
+
+// second loop: beta = (y_j^T psi) / (y_j^T s_j);  psi += s_j (lambda_j - beta)
+__global__ void k_lbfgs_loop2(int64_t n, float* __restrict__ psi, const float* __restrict__ sj,
+                              const double* __restrict__ sc, int np, int j) {
+  const double beta = sc[2 * np] / sc[j];
+  const float coef = (float)(sc[np + j] - beta);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    psi[i] += coef * sj[i];
+}
+
+}  // namespace pat

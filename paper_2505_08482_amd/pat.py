@@ -1,0 +1,227 @@
+"""Thin Python binding of the C ABI in ``include/pat.h`` (``libpat.so``).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Arrays are torch tensors on the GPU (float32, contiguous); the work
+is enqueued on torch's current stream.  Importing this module never falls back
+to anything: if the library is missing, the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpat.so")
+
+PAT_OK, PAT_EINVAL, PAT_EUNSUPPORTED, PAT_EWORKSPACE, PAT_EHIP = 0, -1, -2, -3, -4
+
+EXPORTS = (
+    "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_misfit",
+    "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_time_interp",
+    "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_dot", "pat_status_string",
+)
+
+
+class PatError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class pat_grid(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nt", ctypes.c_int32), ("pml", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("c_ref", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("pml_alpha", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libpat.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2505_08482_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32, f64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                  ctypes.c_double, ctypes.c_size_t)
+    L.pat_plan_create.argtypes = [ctypes.POINTER(pat_grid), i32, i32, vp, ctypes.POINTER(vp)]
+    L.pat_plan_destroy.argtypes = [vp]
+    L.pat_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.pat_forward.argtypes = [vp, vp, vp, vp, vp, sz, i32, i32, vp]
+    L.pat_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.pat_adjoint_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.pat_project_update.argtypes = [i64, vp, vp, f32, vp, vp, f32, f32, vp]
+    L.pat_prolong.argtypes = [i32, vp, i32, i32, vp, i32, i32, vp]
+    L.pat_time_interp.argtypes = [i32, i32, i32, vp, f64, vp, i32, f64, vp]
+    L.pat_lbfgs_scratch_bytes.argtypes = [i32]
+    L.pat_lbfgs_scratch_bytes.restype = sz
+    L.pat_lbfgs_direction.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp]
+    L.pat_dot.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.pat_status_string.argtypes = [ctypes.c_int]
+    L.pat_status_string.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("pat_lbfgs_scratch_bytes", "pat_status_string"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return lib().pat_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status != PAT_OK:
+        raise PatError(status, what)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _f32(t, n: Optional[int] = None, name: str = "array"):
+    import torch
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, has {t.numel()}")
+    return _ptr(t)
+
+
+def _stream() -> int:
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_grid(g) -> pat_grid:
+    """``pat_grid`` from any object with nx, ny, nt, pml, dx, dt, c_ref, rho0, pml_alpha."""
+    return pat_grid(int(g.nx), int(g.ny), int(g.nt), int(g.pml), float(g.dx), float(g.dt),
+                    float(g.c_ref), float(g.rho0), float(g.pml_alpha))
+
+
+class Plan:
+    """A ``pat_plan``: K datasets on one grid with m sensors."""
+
+    def __init__(self, grid, K: int, sensor_xy):
+        self.grid = grid
+        self.K = int(K)
+        xy = np.ascontiguousarray(np.asarray(sensor_xy, dtype=np.float64))
+        if xy.ndim != 2 or xy.shape[1] != 2:
+            raise ValueError("sensor_xy must be [m][2]")
+        self.m = xy.shape[0]
+        self._g = make_grid(grid)
+        h = ctypes.c_void_p()
+        _check(lib().pat_plan_create(ctypes.byref(self._g), self.K, self.m,
+                                     xy.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)), "pat_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pat_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def field_shape(self):
+        return (self.K, self.grid.ny, self.grid.nx)
+
+    @property
+    def data_shape(self):
+        return (self.K, self.grid.nt, self.m)
+
+    def workspace_size(self, ckpt_every: int = 0) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().pat_workspace_size(self._h, int(ckpt_every), ctypes.byref(b)), "pat_workspace_size")
+        return b.value
+
+    def workspace(self, ckpt_every: int = 0, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_size(ckpt_every), dtype=torch.uint8, device=device)
+
+    def forward(self, c, p0, data, ws, ckpt_every: int = 0, record: bool = True):
+        g = self.grid
+        _check(lib().pat_forward(self._h, _f32(c, g.ny * g.nx, "c"), _f32(p0, self.K * g.ny * g.nx, "p0"),
+                                 _f32(data, self.K * g.nt * self.m, "data"), _ptr(ws), ws.numel(),
+                                 int(ckpt_every), 1 if record else 0, _stream()), "pat_forward")
+
+    def misfit(self, data, y, w, resid, J):
+        import torch
+        n = self.K * self.grid.nt * self.m
+        if J.dtype != torch.float64 or J.numel() < 1:
+            raise ValueError("J must be a float64 device scalar")
+        _check(lib().pat_misfit(self._h, _f32(data, n, "data"), _f32(y, n, "y"), _f32(w, self.K, "w"),
+                                _f32(resid, n, "resid"), _ptr(J), _stream()), "pat_misfit")
+
+    def adjoint_gradient(self, c, p0, resid, g_p0, g_c, ws):
+        g = self.grid
+        N = g.ny * g.nx
+        _check(lib().pat_adjoint_gradient(self._h, _f32(c, N, "c"), _f32(p0, self.K * N, "p0"),
+                                          _f32(resid, self.K * g.nt * self.m, "resid"),
+                                          _f32(g_p0, self.K * N, "g_p0"), _f32(g_c, N, "g_c"),
+                                          _ptr(ws), ws.numel(), _stream()), "pat_adjoint_gradient")
+
+
+def project_update(x, d, alpha: float, lo=None, hi=None, lo_s: float = -np.inf, hi_s: float = np.inf):
+    n = x.numel()
+    _check(lib().pat_project_update(n, _f32(x, n, "x"), _f32(d, n, "d"), float(alpha),
+                                    None if lo is None else _f32(lo, n, "lo"),
+                                    None if hi is None else _f32(hi, n, "hi"), float(lo_s), float(hi_s),
+                                    _stream()), "pat_project_update")
+
+
+def prolong(coarse, fine):
+    """``coarse [nchan][nyc][nxc]`` -> ``fine [nchan][nyf][nxf]``."""
+    nchan, nyc, nxc = coarse.shape
+    nchan2, nyf, nxf = fine.shape
+    if nchan != nchan2:
+        raise ValueError("channel mismatch")
+    _check(lib().pat_prolong(nchan, _f32(coarse), nyc, nxc, _f32(fine), nyf, nxf, _stream()), "pat_prolong")
+
+
+def time_interp(y, dt_src: float, out, dt_dst: float):
+    """``y [nlead][nt_src][m]`` -> ``out [nlead][nt_dst][m]``."""
+    nlead, nt_src, m = y.shape
+    nlead2, nt_dst, m2 = out.shape
+    if nlead != nlead2 or m != m2:
+        raise ValueError("shape mismatch")
+    _check(lib().pat_time_interp(nlead, nt_src, m, _f32(y), float(dt_src), _f32(out), nt_dst, float(dt_dst),
+                                 _stream()), "pat_time_interp")
+
+
+def lbfgs_scratch_bytes(npairs: int) -> int:
+    return int(lib().pat_lbfgs_scratch_bytes(int(npairs)))
+
+
+def lbfgs_direction(g, s_list: Sequence, y_list: Sequence, d, scratch):
+    n = g.numel()
+    npairs = len(s_list)
+    S = (ctypes.c_void_p * max(npairs, 1))(*[_f32(s, n, "s") for s in s_list])
+    Y = (ctypes.c_void_p * max(npairs, 1))(*[_f32(y, n, "y") for y in y_list])
+    _check(lib().pat_lbfgs_direction(n, _f32(g, n, "g"), npairs, ctypes.cast(S, ctypes.c_void_p),
+                                     ctypes.cast(Y, ctypes.c_void_p), _f32(d, n, "d"), _ptr(scratch), _stream()),
+           "pat_lbfgs_direction")
+
+
+def dot(a, b, out, scratch):
+    n = a.numel()
+    _check(lib().pat_dot(n, _f32(a, n, "a"), _f32(b, n, "b"), _ptr(out), _ptr(scratch), _stream()), "pat_dot")

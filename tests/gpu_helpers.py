@@ -1,0 +1,74 @@
+"""Shared helpers of the GPU tests: run the HIP path through the C ABI and the
+oracle on the same float32-rounded inputs."""
+import sys
+
+import numpy as np
+
+from oracle import kspace
+from paper_2505_08482_amd import inputs as I
+
+
+def announce(msg: str) -> None:
+    print(f"\n[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make_case(wl, config=2, seed_case=0, c_scale=1.0):
+    """float32-rounded c, p0, and a residual from data of a different c."""
+    c, p0 = I.phantoms(wl, config, case=seed_case)
+    c32 = c.astype(np.float32)
+    p032 = p0.astype(np.float32)
+    return c32, p032
+
+
+def gpu_forward_adjoint(wl, c32, p032, resid32=None, ckpt_every=0, torch=None):
+    import torch as _t
+    from paper_2505_08482_amd import pat
+    torch = torch or _t
+    g = wl.grid
+    plan = pat.Plan(g, wl.K, wl.sensors)
+    dev = "cuda"
+    c = torch.from_numpy(c32).to(dev)
+    p0 = torch.from_numpy(p032).to(dev)
+    data = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
+    ws = plan.workspace(ckpt_every)
+    plan.forward(c, p0, data, ws, ckpt_every=ckpt_every, record=True)
+    out = {"data": data.cpu().numpy()}
+    if resid32 is not None:
+        r = torch.from_numpy(np.ascontiguousarray(resid32)).to(dev)
+        gp0 = torch.empty(plan.field_shape, dtype=torch.float32, device=dev)
+        gc = torch.empty((g.ny, g.nx), dtype=torch.float32, device=dev)
+        plan.adjoint_gradient(c, p0, r, gp0, gc, ws)
+        out["g_p0"] = gp0.cpu().numpy()
+        out["g_c"] = gc.cpu().numpy()
+    torch.cuda.synchronize()
+    plan.close()
+    return out
+
+
+def oracle_forward_adjoint(wl, c32, p032, y=None, w=None):
+    """Oracle data; if ``y`` is given also the misfit residual and gradients."""
+    g = wl.grid
+    c = c32.astype(np.float64)
+    p0 = p032.astype(np.float64)
+    data, hist = kspace.forward(g, wl.sensors, c, p0, record=y is not None)
+    out = {"data": data}
+    if y is not None:
+        resid, J = kspace.misfit(data, y, w)
+        gp0, gc = kspace.adjoint_gradient(g, wl.sensors, c, p0, resid, hist)
+        out.update(resid=resid, J=J, g_p0=gp0, g_c=gc)
+    return out
+
+
+def observed_data(wl, c_true32, p032, noise_seed):
+    """Noisy data of the true medium (oracle forward + 1 % noise)."""
+    clean, _ = kspace.forward(wl.grid, wl.sensors, c_true32.astype(np.float64), p032.astype(np.float64),
+                              record=False)
+    y, sigma = I.add_noise(clean, noise_seed)
+    return y, 1.0 / sigma

@@ -1,0 +1,108 @@
+"""GPU vs oracle parity of the vector entry points of the C ABI:
+misfit (eq. (4)), projected update (eq. (10)-(11)), prolongation (Sec. 3.1),
+time resampling (Sec. 4.1.2) and the two-loop recursion (Alg. 1)."""
+import numpy as np
+import pytest
+
+from oracle import kspace, optim
+from paper_2505_08482_amd import inputs as I
+from gpu_helpers import announce, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def test_misfit(torch):
+    from paper_2505_08482_amd import pat
+    wl = I.config2(n=64, K=3, nt=37)
+    plan = pat.Plan(wl.grid, wl.K, wl.sensors)
+    rng = np.random.default_rng(0)
+    d = rng.standard_normal(plan.data_shape).astype(np.float32)
+    y = rng.standard_normal(plan.data_shape).astype(np.float32)
+    w = np.array([2.0, 0.5, 3.0], dtype=np.float32)
+    r_o, J_o = kspace.misfit(d.astype(np.float64), y.astype(np.float64), w.astype(np.float64))
+    announce("misfit")
+    T = lambda a: torch.from_numpy(a).cuda()
+    r = torch.empty_like(T(d))
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan.misfit(T(d), T(y), T(w), r, J)
+    assert rel_l2(r.cpu().numpy(), r_o) < 1e-6
+    assert abs(J.item() - J_o) < 1e-6 * J_o
+    plan.close()
+
+
+def test_project_update(torch):
+    from paper_2505_08482_amd import pat
+    rng = np.random.default_rng(1)
+    n = 100003
+    x = rng.uniform(1300, 1700, n).astype(np.float32)
+    d = rng.standard_normal(n).astype(np.float32) * 100
+    lo = np.full(n, 1400, np.float32)
+    hi = np.full(n, 1600, np.float32)
+    lo[:10] = hi[:10] = 1500.0
+    announce("project_update")
+    xg = torch.from_numpy(x.copy()).cuda()
+    pat.project_update(xg, torch.from_numpy(d).cuda(), 0.5, torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda())
+    ref = optim.project_update(x.astype(np.float64), d.astype(np.float64), 0.5, lo, hi)
+    assert np.array_equal(xg.cpu().numpy(), ref.astype(np.float32))
+    xg = torch.from_numpy(x.copy()).cuda()
+    pat.project_update(xg, torch.from_numpy(d).cuda(), 2.0, lo_s=0.0, hi_s=np.inf)
+    ref = optim.project_update(x.astype(np.float64), d.astype(np.float64), 2.0, 0.0, np.inf)
+    assert np.array_equal(xg.cpu().numpy(), ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("shape", [((3, 16, 16), (3, 32, 32)), ((2, 128, 128), (2, 256, 256)),
+                                   ((1, 64, 48), (1, 96, 72))])
+def test_prolong(torch, shape):
+    from paper_2505_08482_amd import pat
+    (nc, nyc, nxc), (_, nyf, nxf) = shape
+    rng = np.random.default_rng(2)
+    coarse = rng.uniform(1400, 1600, (nc, nyc, nxc)).astype(np.float32)
+    announce(f"prolong {shape}")
+    fine = torch.empty((nc, nyf, nxf), dtype=torch.float32, device="cuda")
+    pat.prolong(torch.from_numpy(coarse).cuda(), fine)
+    ref = np.stack([np.stack([optim.prolong(coarse[i].astype(np.float64)[None], nyf, nxf)[0]]) for i in range(nc)])[:, 0]
+    assert np.abs(fine.cpu().numpy() - ref).max() < 1e-3
+
+
+def test_time_interp(torch):
+    from paper_2505_08482_amd import pat
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((2, 401, 7)).astype(np.float32)
+    announce("time_interp")
+    for dt_dst, nt_dst in ((4.0, 101), (2.0, 201), (3.3, 130)):
+        out = torch.empty((2, nt_dst, 7), dtype=torch.float32, device="cuda")
+        pat.time_interp(torch.from_numpy(y).cuda(), 1.0, out, dt_dst)
+        ref = optim.time_interp(y.astype(np.float64), 1.0, dt_dst, nt_dst)
+        assert np.abs(out.cpu().numpy() - ref).max() < 1e-5
+    out = torch.empty((2, 101, 7), dtype=torch.float32, device="cuda")
+    pat.time_interp(torch.from_numpy(y).cuda(), 1.0, out, 4.0)
+    assert np.array_equal(out.cpu().numpy(), y[:, ::4])
+
+
+@pytest.mark.parametrize("npairs", [0, 1, 5, 20])
+def test_lbfgs_direction_and_dot(torch, npairs):
+    from paper_2505_08482_amd import pat
+    rng = np.random.default_rng(4 + npairs)
+    n = 50000
+    diag = rng.uniform(0.5, 2.0, n)
+    s_list = [rng.standard_normal(n).astype(np.float32) for _ in range(npairs)]
+    y_list = [(diag * s).astype(np.float32) for s in s_list]
+    g = rng.standard_normal(n).astype(np.float32)
+    ref = optim.lbfgs_direction(g.astype(np.float64), [s.astype(np.float64) for s in s_list],
+                                [y.astype(np.float64) for y in y_list])
+    announce(f"lbfgs npairs={npairs}")
+    T = lambda a: torch.from_numpy(a).cuda()
+    scratch = torch.empty(pat.lbfgs_scratch_bytes(npairs), dtype=torch.uint8, device="cuda")
+    d = torch.empty(n, dtype=torch.float32, device="cuda")
+    pat.lbfgs_direction(T(g), [T(s) for s in s_list], [T(y) for y in y_list], d, scratch)
+    assert rel_l2(d.cpu().numpy(), ref) < 1e-5
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    pat.dot(T(g), T(g), out, scratch)
+    assert abs(out.item() - float(np.dot(g.astype(np.float64), g.astype(np.float64)))) < 1e-9 * out.item()

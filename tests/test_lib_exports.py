@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/pat.h (no GPU needed: nothing is computed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2505_08482_amd import pat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pat.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pat_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(pat.EXPORTS)
+
+
+@pytest.mark.skipif(not os.path.exists(pat.LIB_PATH), reason="libpat.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(pat.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(pat.LIB_PATH), reason="libpat.so not built")
+def test_host_side_argument_checks():
+    """Invalid arguments are rejected before anything touches a device."""
+    L = pat.lib()
+    assert L.pat_plan_create(None, 1, 1, None, None) == pat.PAT_EINVAL
+    g = pat.pat_grid(100, 100, 10, 10, 1e-4, 1e-8, 1600.0, 1000.0, 2.0)   # 100 has no radix plan
+    xy = (ctypes.c_double * 2)(0.0, 0.0)
+    h = ctypes.c_void_p()
+    assert L.pat_plan_create(ctypes.byref(g), 1, 1, xy, ctypes.byref(h)) == pat.PAT_EUNSUPPORTED
+    g = pat.pat_grid(64, 64, 0, 10, 1e-4, 1e-8, 1600.0, 1000.0, 2.0)      # nt = 0
+    assert L.pat_plan_create(ctypes.byref(g), 1, 1, xy, ctypes.byref(h)) == pat.PAT_EINVAL
+    assert L.pat_project_update(-1, None, None, 1.0, None, None, 0.0, 1.0, None) == pat.PAT_EINVAL
+    assert L.pat_prolong(0, None, 1, 1, None, 1, 1, None) == pat.PAT_EINVAL
+    assert pat.status_string(pat.PAT_EWORKSPACE).startswith("workspace")
