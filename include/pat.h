@@ -139,6 +139,29 @@ int pat_lbfgs_direction(int64_t n, const float* g, int32_t npairs, const float* 
  * with npairs = 0). */
 int pat_dot(int64_t n, const float* a, const float* b, double* out, void* scratch, void* stream);
 
+/* Kernel timing (diagnostics).  Kinds of fused pass, in time-step order:
+ * forward column GRAD, row U, column DIV, row RHO; adjoint column SUMM, row
+ * RHO, column GRAD, row U. */
+#define PAT_PASS_FWD_COL_GRAD 0
+#define PAT_PASS_FWD_ROW_U    1
+#define PAT_PASS_FWD_COL_DIV  2
+#define PAT_PASS_FWD_ROW_RHO  3
+#define PAT_PASS_ADJ_COL_SUMM 4
+#define PAT_PASS_ADJ_ROW_RHO  5
+#define PAT_PASS_ADJ_COL_GRAD 6
+#define PAT_PASS_ADJ_ROW_U    7
+#define PAT_PASS_KINDS        8
+/* pat_trace_start(every): from now on every `every`-th launch of each pass
+ * kind is bracketed by two HIP events recorded on the stream it is launched
+ * on (at most 1024 launches per kind; the events are created here, on the
+ * current device).  pat_trace_stop() stops recording.  pat_trace_read(kind,
+ * &count, &total_ms): once those streams have drained, the number of timed
+ * launches of `kind` and their summed duration in milliseconds.  Process-wide
+ * state: not for concurrent use from several threads. */
+int pat_trace_start(int32_t every);
+int pat_trace_stop(void);
+int pat_trace_read(int32_t kind, int64_t* count, double* total_ms);
+
 const char* pat_status_string(int status);
 
 #ifdef __cplusplus

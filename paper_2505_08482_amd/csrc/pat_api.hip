@@ -37,6 +37,35 @@ int grid_blocks(int64_t n, int threads = 256) {
   return (int)std::max<int64_t>(b, 1);
 }
 
+// ---------------------------------------------------------------------------
+// Launch timing (pat_trace_*): sampled event pairs per pass kind
+// ---------------------------------------------------------------------------
+constexpr int kTraceCap = 1024;
+struct Trace {
+  bool on = false;
+  int every = 1;
+  bool created = false;
+  int64_t seen[PAT_PASS_KINDS] = {};
+  int used[PAT_PASS_KINDS] = {};
+  std::vector<hipEvent_t> ev;   // [kind][cap][2]
+};
+Trace g_trace;
+
+struct TraceScope {
+  int slot = -1, kind;
+  hipStream_t st;
+  TraceScope(int kind_, hipStream_t st_) : kind(kind_), st(st_) {
+    if (!g_trace.on) return;
+    const int64_t s = g_trace.seen[kind]++;
+    if (s % g_trace.every != 0 || g_trace.used[kind] >= kTraceCap) return;
+    slot = g_trace.used[kind]++;
+    (void)hipEventRecord(g_trace.ev[((size_t)kind * kTraceCap + slot) * 2], st);
+  }
+  ~TraceScope() {
+    if (slot >= 0) (void)hipEventRecord(g_trace.ev[((size_t)kind * kTraceCap + slot) * 2 + 1], st);
+  }
+};
+
 }  // namespace
 
 struct pat_plan {
@@ -132,6 +161,7 @@ int launch_fwd_init(const pat_plan* p, hipStream_t st, const float* c, const flo
 }
 
 int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2* SA, float2* SB, int first) {
+  TraceScope ts(PAT_PASS_FWD_ROW_U, st);
   switch (p->g.nx) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
@@ -146,6 +176,7 @@ int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2
 
 int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx, float* ry, float* hist,
                    float* dpart_n, float2* SA, float2* SB) {
+  TraceScope ts(PAT_PASS_FWD_ROW_RHO, st);
   switch (p->g.nx) {
 #define X(N)                                                                                               \
   case N:                                                                                                  \
@@ -161,6 +192,11 @@ int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx,
 
 template <int MODE>
 int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float scale) {
+  constexpr int kind = MODE == COL_GRAD1 ? PAT_PASS_FWD_COL_GRAD
+                       : MODE == COL_PAIRM ? PAT_PASS_FWD_COL_DIV
+                       : MODE == COL_SUMM  ? PAT_PASS_ADJ_COL_SUMM
+                                           : PAT_PASS_ADJ_COL_GRAD;
+  TraceScope ts(kind, st);
   switch (p->g.ny) {
 #define X(N)                                                                                                 \
   case N:                                                                                                    \
@@ -176,6 +212,7 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
 
 int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const float* p_n, const float* resid_n,
                    float* rhx, float* rhy, float* gck, float2* SA, float2* SB) {
+  TraceScope ts(PAT_PASS_ADJ_ROW_RHO, st);
   switch (p->g.nx) {
 #define X(N)                                                                                                \
   case N:                                                                                                   \
@@ -190,6 +227,7 @@ int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const floa
 }
 
 int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, float2* SA, float2* SB, int final_) {
+  TraceScope ts(PAT_PASS_ADJ_ROW_U, st);
   switch (p->g.nx) {
 #define X(N)                                                                                                     \
   case N:                                                                                                        \
@@ -640,6 +678,43 @@ int pat_lbfgs_direction(int64_t n, const float* g, int32_t np, const float* cons
     hipLaunchKernelGGL(k_lbfgs_loop2, dim3(blocks), dim3(256), 0, st, n, d, s[j], sc, np, j);
     PAT_TRY(last_error());
   }
+  return PAT_OK;
+}
+
+int pat_trace_start(int32_t every) {
+  if (every <= 0) return PAT_EINVAL;
+  if (!g_trace.created) {
+    g_trace.ev.resize((size_t)PAT_PASS_KINDS * kTraceCap * 2);
+    for (auto& e : g_trace.ev)
+      if (hipEventCreate(&e) != hipSuccess) return PAT_EHIP;
+    g_trace.created = true;
+  }
+  for (int k = 0; k < PAT_PASS_KINDS; ++k) {
+    g_trace.seen[k] = 0;
+    g_trace.used[k] = 0;
+  }
+  g_trace.every = every;
+  g_trace.on = true;
+  return PAT_OK;
+}
+
+int pat_trace_stop(void) {
+  g_trace.on = false;
+  return PAT_OK;
+}
+
+int pat_trace_read(int32_t kind, int64_t* count, double* total_ms) {
+  if (kind < 0 || kind >= PAT_PASS_KINDS || !count || !total_ms) return PAT_EINVAL;
+  double tot = 0.0;
+  for (int i = 0; i < g_trace.used[kind]; ++i) {
+    float ms = 0.f;
+    hipEvent_t a = g_trace.ev[((size_t)kind * kTraceCap + i) * 2];
+    hipEvent_t b = g_trace.ev[((size_t)kind * kTraceCap + i) * 2 + 1];
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) return PAT_EHIP;
+    tot += ms;
+  }
+  *count = g_trace.used[kind];
+  *total_ms = tot;
   return PAT_OK;
 }
 

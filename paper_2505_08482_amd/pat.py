@@ -22,7 +22,11 @@ EXPORTS = (
     "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_misfit",
     "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_time_interp",
     "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_dot", "pat_status_string",
+    "pat_trace_start", "pat_trace_stop", "pat_trace_read",
 )
+
+PASS_KINDS = ("fwd_col_grad", "fwd_row_u", "fwd_col_div", "fwd_row_rho",
+              "adj_col_summ", "adj_row_rho", "adj_col_grad", "adj_row_u")
 
 
 class PatError(RuntimeError):
@@ -65,6 +69,9 @@ def lib() -> ctypes.CDLL:
     L.pat_lbfgs_scratch_bytes.restype = sz
     L.pat_lbfgs_direction.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp]
     L.pat_dot.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.pat_trace_start.argtypes = [i32]
+    L.pat_trace_stop.argtypes = []
+    L.pat_trace_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     L.pat_status_string.argtypes = [ctypes.c_int]
     L.pat_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -225,3 +232,23 @@ def lbfgs_direction(g, s_list: Sequence, y_list: Sequence, d, scratch):
 def dot(a, b, out, scratch):
     n = a.numel()
     _check(lib().pat_dot(n, _f32(a, n, "a"), _f32(b, n, "b"), _ptr(out), _ptr(scratch), _stream()), "pat_dot")
+
+
+def trace_start(every: int = 1):
+    """Time every ``every``-th launch of each fused pass with HIP events."""
+    _check(lib().pat_trace_start(int(every)), "pat_trace_start")
+
+
+def trace_stop():
+    _check(lib().pat_trace_stop(), "pat_trace_stop")
+
+
+def trace_read():
+    """``{pass kind: (timed launches, summed ms)}`` (waits for the events)."""
+    out = {}
+    for i, name in enumerate(PASS_KINDS):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(lib().pat_trace_read(i, ctypes.byref(n), ctypes.byref(ms)), "pat_trace_read")
+        out[name] = (n.value, ms.value)
+    return out
