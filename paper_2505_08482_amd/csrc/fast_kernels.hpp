@@ -1,0 +1,643 @@
+// fast_kernels.hpp — register-resident passes for power-of-two grids (32..512).
+//
+// Same arithmetic as wave_kernels.hpp (the k-space scheme of Sec. 2.1 and its
+// exact discrete adjoint), organised for gfx950:
+//  * every thread owns the elements q + T*m (m < 8) of one transform, so the
+//    first Stockham stage reads straight from HBM, the last stage leaves the
+//    result where the fused physics and the next transform's first stage want
+//    it, and only the inner stages exchange through LDS;
+//  * twiddles live in registers, loaded once per kernel from the float64-exact
+//    table;
+//  * half spectra are folded: the real Nyquist bin of a row is stored in the
+//    imaginary part of its (real) DC bin, so a row spectrum has exactly nx/2
+//    complex entries and the column pass has nx/2 columns.  The column holding
+//    DC + i * Nyquist is two real sequences along y; it is split with the usual
+//    two-for-one identity, each half multiplied by its own wavenumber, and
+//    recombined before the inverse column transform.
+//  * row passes run one 64-thread block per (T threads x 2 rows) group set;
+//    column passes load 8..64 adjacent columns per block so that every load
+//    instruction touches contiguous 64-256 byte row segments.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_lds.hpp"
+#include "wave_kernels.hpp"
+
+namespace pat {
+namespace fast {
+
+template <int N> struct Cfg;
+template <> struct Cfg<512> { static constexpr int T = 64; using L = RList<8, 8, 8>; static constexpr int TC = 8; };
+template <> struct Cfg<256> { static constexpr int T = 32; using L = RList<8, 8, 4>; static constexpr int TC = 8; };
+template <> struct Cfg<128> { static constexpr int T = 16; using L = RList<8, 4, 4>; static constexpr int TC = 16; };
+template <> struct Cfg<64>  { static constexpr int T = 8;  using L = RList<8, 8>;    static constexpr int TC = 32; };
+template <> struct Cfg<32>  { static constexpr int T = 4;  using L = RList<8, 4>;    static constexpr int TC = 64; };
+
+// LDS position of element i: one pad slot per 8 keeps the radix-8 exchanges
+// (stride-8 writes, stride-1 reads) free of bank conflicts.
+__device__ __forceinline__ int phys(int i) { return i + (i >> 3); }
+template <int N> struct Lds { static constexpr int P = N + N / 8 + 8; };   // pitch of one transform
+
+// One register-resident Stockham stage on NV transforms at once (shared barriers).
+template <int N, int T, int R, int NS, int DIR, bool LAST, int NV>
+__device__ __forceinline__ void rstage(float2 (*v)[8], const float2* w, float2* const* lds, int q) {
+  constexpr int B = 8 / R;
+  float2 y[NV][B][R];
+#pragma unroll
+  for (int t = 0; t < NV; ++t)
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[t][b][r] = v[t][b + r * B];
+  if (NS > 1) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 tw = w[b * (R - 1) + r - 1];
+        if (DIR > 0) tw.y = -tw.y;
+#pragma unroll
+        for (int t = 0; t < NV; ++t) y[t][b][r] = cmul(y[t][b][r], tw);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < NV; ++t)
+#pragma unroll
+    for (int b = 0; b < B; ++b) Dft<R, DIR>::run(y[t][b]);
+  if (LAST) {
+#pragma unroll
+    for (int t = 0; t < NV; ++t)
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[t][b + r * B] = y[t][b][r];
+    return;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = q + T * b;
+    const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int t = 0; t < NV; ++t)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[t][phys(base + r * NS)] = y[t][b][r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < NV; ++t)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[t][m] = lds[t][phys(q + T * m)];
+}
+
+template <int N, typename L> struct RegFft;
+
+template <int N, int R1, int R2, int R3> struct RegFft<N, RList<R1, R2, R3>> {
+  static constexpr int T = Cfg<N>::T, NS2 = R1, NS3 = R1 * R2;
+  float2 w2[(8 / R2) * (R2 - 1)];
+  float2 w3[(8 / R3) * (R3 - 1)];
+  __device__ __forceinline__ void init(const float2* __restrict__ tw, int q) {
+#pragma unroll
+    for (int b = 0; b < 8 / R2; ++b)
+#pragma unroll
+      for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] = tw[(r * ((q + T * b) % NS2)) * (N / (NS2 * R2))];
+#pragma unroll
+    for (int b = 0; b < 8 / R3; ++b)
+#pragma unroll
+      for (int r = 1; r < R3; ++r) w3[b * (R3 - 1) + r - 1] = tw[(r * ((q + T * b) % NS3)) * (N / (NS3 * R3))];
+  }
+  template <int DIR, int NV>
+  __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
+    rstage<N, T, R1, 1, DIR, false, NV>(v, nullptr, lds, q);
+    rstage<N, T, R2, NS2, DIR, false, NV>(v, w2, lds, q);
+    rstage<N, T, R3, NS3, DIR, true, NV>(v, w3, lds, q);
+  }
+};
+
+template <int N, int R1, int R2> struct RegFft<N, RList<R1, R2>> {
+  static constexpr int T = Cfg<N>::T, NS2 = R1;
+  float2 w2[(8 / R2) * (R2 - 1)];
+  __device__ __forceinline__ void init(const float2* __restrict__ tw, int q) {
+#pragma unroll
+    for (int b = 0; b < 8 / R2; ++b)
+#pragma unroll
+      for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] = tw[(r * ((q + T * b) % NS2)) * (N / (NS2 * R2))];
+  }
+  template <int DIR, int NV>
+  __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
+    rstage<N, T, R1, 1, DIR, false, NV>(v, nullptr, lds, q);
+    rstage<N, T, R2, NS2, DIR, true, NV>(v, w2, lds, q);
+  }
+};
+
+template <int N> using Fft = RegFft<N, typename Cfg<N>::L>;
+
+// ---------------------------------------------------------------------------
+// Folded half spectra along a row of length N (h = N/2 entries)
+// ---------------------------------------------------------------------------
+// z[k] = a[k] + i b[k] for the two real rows whose folded spectra are A, B.
+__device__ __forceinline__ float2 pack_folded(const float2* __restrict__ A, const float2* __restrict__ B, int k,
+                                              int N) {
+  const int h = N >> 1;
+  if (k == 0) return make_float2(A[0].x, B[0].x);
+  if (k == h) return make_float2(A[0].y, B[0].y);
+  if (k < h) {
+    const float2 a = A[k], b = B[k];
+    return make_float2(a.x - b.y, a.y + b.x);
+  }
+  const float2 a = A[N - k], b = B[N - k];
+  return make_float2(a.x + b.y, b.x - a.y);
+}
+
+// Split the transform of a + i b (held in owner layout, element q + T m in v[m])
+// into the folded spectra of a and b and store them (rows rowA, rowB).
+template <int N>
+__device__ __forceinline__ void unpack_store(const float2 (&v)[8], int q, int lane_base, float2* __restrict__ rowA,
+                                             float2* __restrict__ rowB) {
+  constexpr int T = Cfg<N>::T;
+  float2 part[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int src = lane_base + ((T - q) & (T - 1));
+    const float px = __shfl(v[7 - m].x, src);
+    const float py = __shfl(v[7 - m].y, src);
+    part[m] = q == 0 ? v[(8 - m) & 7] : make_float2(px, py);
+  }
+  // owned k = q + T m <= N/2 : m < 4, or m == 4 for q == 0 (the Nyquist bin)
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int k = q + T * m;
+    const float2 P = v[m], Q = make_float2(part[m].x, -part[m].y);   // Z[k], conj Z[N-k]
+    const float2 A = make_float2(0.5f * (P.x + Q.x), 0.5f * (P.y + Q.y));
+    const float2 B = make_float2(0.5f * (P.y - Q.y), -0.5f * (P.x - Q.x));
+    if (k == 0) {
+      const float2 Zn = v[4];   // k = N/2 belongs to q = 0, m = 4: A = Re, B = Im
+      rowA[0] = make_float2(P.x, Zn.x);
+      rowB[0] = make_float2(P.y, Zn.y);
+    } else {
+      rowA[k] = A;
+      rowB[k] = B;
+    }
+  }
+}
+
+// ===========================================================================
+// Row passes: 64-thread blocks, G = 64/T groups of T threads, 2 rows per group
+// ===========================================================================
+template <int N> struct RowF {
+  static constexpr int T = Cfg<N>::T;
+  static constexpr int G = 64 / T;
+  static constexpr int ROWS = 2 * G;
+};
+
+#define PAT_ROW_PROLOGUE(N)                                                    \
+  using RC = RowF<N>;                                                          \
+  constexpr int T = RC::T;                                                     \
+  const int K = tb.K, ny = tb.ny, nhf = N / 2;                                 \
+  const int k = blockIdx.x % K, ybase = (blockIdx.x / K) * RC::ROWS;           \
+  const int tid = threadIdx.x, grp = tid / T, q = tid % T, lane_base = grp * T; \
+  const int y0 = ybase + 2 * grp, y1 = y0 + 1;                                 \
+  (void)nhf;                                                                   \
+  Fft<N> fft;                                                                  \
+  fft.init(tb.tw_x, q);
+
+// n = 0: rho = p0/(2c^2), history, sensors, spectra of p0 (rows y0, y1 share one FFT)
+template <int N>
+__global__ __launch_bounds__(64) void k_fwd_init(Tables tb, const float* __restrict__ c, const float* __restrict__ p0,
+                                                 float* __restrict__ rx, float* __restrict__ ry,
+                                                 float* __restrict__ hist0, float* __restrict__ dpart,
+                                                 float2* __restrict__ SA) {
+  PAT_ROW_PROLOGUE(N)
+  __shared__ float2 X[RC::G][Lds<N>::P];
+  __shared__ float P[RC::ROWS][N];
+  float2 v[1][8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int x = q + T * m;
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int y = y0 + h;
+      if (y < ny) {
+        const size_t i = ((size_t)k * ny + y) * N + x;
+        const float val = p0[i];
+        const float cc = c[(size_t)y * N + x];
+        const float rr = val * (0.5f / (cc * cc));
+        rx[i] = rr;
+        ry[i] = rr;
+        if (hist0) hist0[i] = val;
+        (h == 0 ? a : b) = val;
+      }
+    }
+    P[2 * grp][x] = a;
+    P[2 * grp + 1][x] = b;
+    v[0][m] = make_float2(a, b);
+  }
+  __syncthreads();
+  if (dpart) gather_rows<N, 64>(tb, &P[0][0], ybase, RC::ROWS, dpart + (size_t)k * tb.nt * 2 * tb.m, tid);
+  float2* L[1] = {X[grp]};
+  fft.template run<-1, 1>(v, L, q);
+  float2* ra = SA + ((size_t)k * ny + min(y0, ny - 1)) * nhf;
+  float2* rb = SA + ((size_t)k * ny + min(y1, ny - 1)) * nhf;
+  if (y1 < ny) unpack_store<N>(v[0], q, lane_base, ra, rb);
+}
+
+// velocity update (first != 0: u^{-1/2} = G/2), spectra of (u_x + i u_y)
+template <int N>
+__global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux, float* __restrict__ uy,
+                                              float2* __restrict__ SA, float2* __restrict__ SB, int first) {
+  PAT_ROW_PROLOGUE(N)
+  __shared__ float2 X[RC::G][2][Lds<N>::P];
+  float2 v[2][8];
+  float ox[2][8], oy[2][8];
+  const bool ok = y1 < ny;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float2* A = SA + ((size_t)k * ny + y) * nhf;
+    const float2* B = SB + ((size_t)k * ny + y) * nhf;
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      v[h][m] = pack_folded(A, B, q + T * m, N);
+      if (!first) {
+        ox[h][m] = ux[f + q + T * m];
+        oy[h][m] = uy[f + q + T * m];
+      }
+    }
+  }
+  float2* L[2] = {X[grp][0], X[grp][1]};
+  fft.template run<+1, 2>(v, L, q);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float ays = tb.asy[y];
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int x = q + T * m;
+      const float2 g = v[h][m];
+      const float axs = tb.asx[x];
+      const float uxo = first ? 0.5f * g.x : ox[h][m];
+      const float uyo = first ? 0.5f * g.y : oy[h][m];
+      const float nux = axs * (axs * uxo - g.x);
+      const float nuy = ays * (ays * uyo - g.y);
+      if (ok) {
+        ux[f + x] = nux;
+        uy[f + x] = nuy;
+      }
+      v[h][m] = make_float2(nux, nuy);
+    }
+  }
+  fft.template run<-1, 2>(v, L, q);
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const size_t r = ((size_t)k * ny + y0 + h) * nhf;
+      unpack_store<N>(v[h], q, lane_base, SA + r, SB + r);
+    }
+  }
+}
+
+// density / pressure update, history, sensors at n+1, spectra of p (rows y0, y1 share one FFT)
+template <int N>
+__global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restrict__ c, float* __restrict__ rx,
+                                                float* __restrict__ ry, float* __restrict__ hist,
+                                                float* __restrict__ dpart_n, float2* __restrict__ SA,
+                                                const float2* __restrict__ SB) {
+  PAT_ROW_PROLOGUE(N)
+  __shared__ float2 X[RC::G][2][Lds<N>::P];
+  __shared__ float P[RC::ROWS][N];
+  float2 v[2][8];
+  float orx[2][8], ory[2][8], cc[2][8];
+  const bool ok = y1 < ny;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float2* A = SA + ((size_t)k * ny + y) * nhf;
+    const float2* B = SB + ((size_t)k * ny + y) * nhf;
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int x = q + T * m;
+      v[h][m] = pack_folded(A, B, x, N);
+      orx[h][m] = rx[f + x];
+      ory[h][m] = ry[f + x];
+      cc[h][m] = c[(size_t)y * N + x];
+    }
+  }
+  float2* L[2] = {X[grp][0], X[grp][1]};
+  fft.template run<+1, 2>(v, L, q);
+  float2 z[1][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float ays = tb.ay[y];
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int x = q + T * m;
+      const float2 d = v[h][m];
+      const float axs = tb.ax[x];
+      const float nrx = axs * (axs * orx[h][m] - d.x);
+      const float nry = ays * (ays * ory[h][m] - d.y);
+      const float p = (cc[h][m] * cc[h][m]) * (nrx + nry);
+      if (ok) {
+        rx[f + x] = nrx;
+        ry[f + x] = nry;
+        if (hist) hist[f + x] = p;
+      }
+      P[2 * grp + h][x] = ok ? p : 0.f;
+      if (h == 0) z[0][m].x = p; else z[0][m].y = p;
+    }
+  }
+  __syncthreads();
+  if (dpart_n) gather_rows<N, 64>(tb, &P[0][0], ybase, RC::ROWS, dpart_n + (size_t)k * tb.nt * 2 * tb.m, tid);
+  float2* L1[1] = {X[grp][0]};
+  fft.template run<-1, 1>(z, L1, q);
+  if (ok) {
+    float2* ra = SA + ((size_t)k * ny + y0) * nhf;
+    float2* rb = SA + ((size_t)k * ny + y1) * nhf;
+    unpack_store<N>(z[0], q, lane_base, ra, rb);
+  }
+}
+
+// adjoint: ph = S^T r^n + (inverse rows of the SUMM spectrum); rh += c^2 ph;
+// gc += (2/c) p^n ph; spectra of (a_x rh_x + i a_y rh_y); rh <- a^2 rh.
+template <int N>
+__global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restrict__ c, const float* __restrict__ p_n,
+                                                const float* __restrict__ resid_n, float* __restrict__ rhx,
+                                                float* __restrict__ rhy, float* __restrict__ gck,
+                                                float2* __restrict__ SA, float2* __restrict__ SB) {
+  PAT_ROW_PROLOGUE(N)
+  __shared__ float2 X[RC::G][2][Lds<N>::P];
+  __shared__ float PH[RC::ROWS][N];
+  const bool ok = y1 < ny;
+  float2 v[1][8];
+  {
+    const float2* A = SA + ((size_t)k * ny + (ok ? y0 : 0)) * nhf;
+    const float2* B = SA + ((size_t)k * ny + (ok ? y1 : 0)) * nhf;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[0][m] = pack_folded(A, B, q + T * m, N);
+  }
+  float2* L1[1] = {X[grp][0]};
+  fft.template run<+1, 1>(v, L1, q);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    PH[2 * grp][q + T * m] = v[0][m].x;
+    PH[2 * grp + 1][q + T * m] = v[0][m].y;
+  }
+  __syncthreads();
+  scatter_rows<N, 64>(tb, &PH[0][0], ybase, RC::ROWS, resid_n + (size_t)k * tb.nt * tb.m, tid);
+  __syncthreads();
+  float2 w[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float ays = tb.ay[y], ay2s = tb.ay2[y];
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int x = q + T * m;
+      const float ph = PH[2 * grp + h][x];
+      const float cv = c[(size_t)y * N + x];
+      const float c2 = cv * cv;
+      const float nrx = rhx[f + x] + c2 * ph;
+      const float nry = rhy[f + x] + c2 * ph;
+      const float gnew = gck[f + x] + (2.0f / cv) * p_n[f + x] * ph;
+      if (ok) {
+        gck[f + x] = gnew;
+        rhx[f + x] = tb.ax2[x] * nrx;
+        rhy[f + x] = ay2s * nry;
+      }
+      w[h][m] = make_float2(tb.ax[x] * nrx, ays * nry);
+    }
+  }
+  float2* L[2] = {X[grp][0], X[grp][1]};
+  fft.template run<-1, 2>(w, L, q);
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const size_t r = ((size_t)k * ny + y0 + h) * nhf;
+      unpack_store<N>(w[h], q, lane_base, SA + r, SB + r);
+    }
+  }
+}
+
+// adjoint velocities: uh <- as^2 uh + (inverse rows of PAIRP spectra);
+// spectra of (w_x uh_x + i w_y uh_y), w = as or as - as^2/2 (final != 0)
+template <int N>
+__global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx, float* __restrict__ uhy,
+                                              float2* __restrict__ SA, float2* __restrict__ SB, int final_) {
+  PAT_ROW_PROLOGUE(N)
+  __shared__ float2 X[RC::G][2][Lds<N>::P];
+  float2 v[2][8];
+  float ox[2][8], oy[2][8];
+  const bool ok = y1 < ny;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float2* A = SA + ((size_t)k * ny + y) * nhf;
+    const float2* B = SB + ((size_t)k * ny + y) * nhf;
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      v[h][m] = pack_folded(A, B, q + T * m, N);
+      ox[h][m] = uhx[f + q + T * m];
+      oy[h][m] = uhy[f + q + T * m];
+    }
+  }
+  float2* L[2] = {X[grp][0], X[grp][1]};
+  fft.template run<+1, 2>(v, L, q);
+  const float* wxt = final_ ? tb.wfx : tb.asx;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float a2y = tb.asy2[y];
+    const float wy = final_ ? tb.wfy[y] : tb.asy[y];
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int x = q + T * m;
+      const float2 g = v[h][m];
+      const float nux = tb.asx2[x] * ox[h][m] + g.x;
+      const float nuy = a2y * oy[h][m] + g.y;
+      if (ok) {
+        uhx[f + x] = nux;
+        uhy[f + x] = nuy;
+      }
+      v[h][m] = make_float2(wxt[x] * nux, wy * nuy);
+    }
+  }
+  fft.template run<-1, 2>(v, L, q);
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const size_t r = ((size_t)k * ny + y0 + h) * nhf;
+      unpack_store<N>(v[h], q, lane_base, SA + r, SB + r);
+    }
+  }
+}
+
+// closing terms of the adjoint: g_p0 and the initial-state part of g_c
+template <int N>
+__global__ __launch_bounds__(64) void k_adj_final(Tables tb, const float* __restrict__ c, const float* __restrict__ p0,
+                                                  const float* __restrict__ resid0, const float* __restrict__ rhx,
+                                                  const float* __restrict__ rhy, float* __restrict__ gck,
+                                                  float* __restrict__ gp0, const float2* __restrict__ SA) {
+  PAT_ROW_PROLOGUE(N)
+  __shared__ float2 X[RC::G][Lds<N>::P];
+  __shared__ float PH[RC::ROWS][N];
+  const bool ok = y1 < ny;
+  float2 v[1][8];
+  {
+    const float2* A = SA + ((size_t)k * ny + (ok ? y0 : 0)) * nhf;
+    const float2* B = SA + ((size_t)k * ny + (ok ? y1 : 0)) * nhf;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[0][m] = pack_folded(A, B, q + T * m, N);
+  }
+  float2* L1[1] = {X[grp]};
+  fft.template run<+1, 1>(v, L1, q);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    PH[2 * grp][q + T * m] = v[0][m].x;
+    PH[2 * grp + 1][q + T * m] = v[0][m].y;
+  }
+  __syncthreads();
+  scatter_rows<N, 64>(tb, &PH[0][0], ybase, RC::ROWS, resid0 + (size_t)k * tb.nt * tb.m, tid);
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int y = y0 + h;
+      const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int x = q + T * m;
+        const float cv = c[(size_t)y * N + x];
+        const float rs = rhx[f + x] + rhy[f + x];
+        gp0[f + x] = PH[2 * grp + h][x] + rs * (0.5f / (cv * cv));
+        gck[f + x] += -(p0[f + x] / (cv * cv * cv)) * rs;
+      }
+    }
+  }
+}
+
+// ===========================================================================
+// Column pass (transform length NY = N), nx/2 folded columns, TC per block
+// ===========================================================================
+template <int N, int MODE>
+__global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
+                                                                float2* __restrict__ SB, float scale) {
+  constexpr int T = Cfg<N>::T, TC = Cfg<N>::TC, P = Lds<N>::P;
+  constexpr bool TWO_IN = MODE != COL_GRAD1;
+  constexpr bool TWO_OUT = MODE != COL_SUMM;
+  __shared__ float2 LA[TC * P];
+  __shared__ float2 LB[(TWO_IN || TWO_OUT) ? TC * P : 1];
+  const int K = tb.K, nx = tb.nx, nhf = nx / 2, nh = tb.nh;
+  const int k = blockIdx.x % K, c0 = (blockIdx.x / K) * TC;
+  const int tid = threadIdx.x, cl = tid % TC, q = tid / TC, cx = c0 + cl;
+  const bool ok = cx < nhf;
+  const size_t base = (size_t)k * N * nhf;
+  Fft<N> fft;
+  fft.init(tb.tw_y, q);
+  float2 a[2][8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const size_t i = base + (size_t)(q + T * m) * nhf + (ok ? cx : 0);
+    a[0][m] = SA[i];
+    if (TWO_IN) a[1][m] = SB[i];
+  }
+  float2* LL[2] = {LA + cl * P, LB + cl * P};
+  if (TWO_IN)
+    fft.template run<-1, 2>(a, LL, q);
+  else
+    fft.template run<-1, 1>(a, LL, q);
+  if (c0 == 0) {
+    // column 0 holds DC + i Nyquist: split by conjugate symmetry along y
+    __syncthreads();
+    if (cl == 0) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        LA[phys(q + T * m)] = a[0][m];
+        if (TWO_IN) LB[phys(q + T * m)] = a[1][m];
+      }
+    }
+    __syncthreads();
+    if (cl == 0) {
+      const float2 e0p = tb.ex_p[0], e0m = tb.ex_m[0], eNp = tb.ex_p[nx / 2], eNm = tb.ex_m[nx / 2];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int e = q + T * m, ep = (N - e) & (N - 1);
+        const float k0 = tb.kappa[(size_t)e * nh] * scale;
+        const float kN = tb.kappa[(size_t)e * nh + nx / 2] * scale;
+        const float2 eyp = tb.ey_p[e], eym = tb.ey_m[e];
+        float2 ZA = a[0][m], ZAp = LA[phys(ep)];
+        // A0 = (Z + conj Zp)/2 (DC column), AN = (Z - conj Zp)/(2i) (Nyquist column)
+        float2 A0 = make_float2(0.5f * (ZA.x + ZAp.x), 0.5f * (ZA.y - ZAp.y));
+        float2 AN = make_float2(0.5f * (ZA.y + ZAp.y), -0.5f * (ZA.x - ZAp.x));
+        float2 B0 = A0, BN = AN;
+        if (TWO_IN) {
+          const float2 ZB = a[1][m], ZBp = LB[phys(ep)];
+          B0 = make_float2(0.5f * (ZB.x + ZBp.x), 0.5f * (ZB.y - ZBp.y));
+          BN = make_float2(0.5f * (ZB.y + ZBp.y), -0.5f * (ZB.x - ZBp.x));
+        }
+        float2 o0, oN, p0_, pN;
+        if (MODE == COL_GRAD1) {
+          o0 = cscale(cmul(A0, e0p), k0); oN = cscale(cmul(AN, eNp), kN);
+          p0_ = cscale(cmul(A0, eyp), k0); pN = cscale(cmul(AN, eyp), kN);
+        } else if (MODE == COL_PAIRP) {
+          o0 = cscale(cmul(A0, e0p), k0); oN = cscale(cmul(AN, eNp), kN);
+          p0_ = cscale(cmul(B0, eyp), k0); pN = cscale(cmul(BN, eyp), kN);
+        } else if (MODE == COL_PAIRM) {
+          o0 = cscale(cmul(A0, e0m), k0); oN = cscale(cmul(AN, eNm), kN);
+          p0_ = cscale(cmul(B0, eym), k0); pN = cscale(cmul(BN, eym), kN);
+        } else {
+          o0 = cscale(cadd(cmul(A0, e0m), cmul(B0, eym)), k0);
+          oN = cscale(cadd(cmul(AN, eNm), cmul(BN, eym)), kN);
+          p0_ = o0; pN = oN;
+        }
+        // recombine: out = o0 + i oN
+        a[0][m] = make_float2(o0.x - oN.y, o0.y + oN.x);
+        if (TWO_OUT) a[1][m] = make_float2(p0_.x - pN.y, p0_.y + pN.x);
+      }
+    }
+  }
+  if (!(c0 == 0 && cl == 0)) {
+    const float2 exp_ = tb.ex_p[ok ? cx : 0], exm = tb.ex_m[ok ? cx : 0];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = q + T * m;
+      const float kap = tb.kappa[(size_t)e * nh + (ok ? cx : 0)] * scale;
+      const float2 x0 = a[0][m];
+      if (MODE == COL_GRAD1) {
+        a[0][m] = cscale(cmul(x0, exp_), kap);
+        a[1][m] = cscale(cmul(x0, tb.ey_p[e]), kap);
+      } else if (MODE == COL_PAIRP) {
+        a[0][m] = cscale(cmul(x0, exp_), kap);
+        a[1][m] = cscale(cmul(a[1][m], tb.ey_p[e]), kap);
+      } else if (MODE == COL_PAIRM) {
+        a[0][m] = cscale(cmul(x0, exm), kap);
+        a[1][m] = cscale(cmul(a[1][m], tb.ey_m[e]), kap);
+      } else {
+        a[0][m] = cscale(cadd(cmul(x0, exm), cmul(a[1][m], tb.ey_m[e])), kap);
+      }
+    }
+  }
+  if (TWO_OUT)
+    fft.template run<+1, 2>(a, LL, q);
+  else
+    fft.template run<+1, 1>(a, LL, q);
+  if (ok) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const size_t i = base + (size_t)(q + T * m) * nhf + cx;
+      SA[i] = a[0][m];
+      if (TWO_OUT) SB[i] = a[1][m];
+    }
+  }
+}
+
+}  // namespace fast
+}  // namespace pat

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -12,6 +13,7 @@
 #include "../../include/pat.h"
 #include "vec_kernels.hpp"
 #include "wave_kernels.hpp"
+#include "fast_kernels.hpp"
 
 using namespace pat;
 
@@ -28,6 +30,10 @@ bool supported(int n) {
 #define PAT_SIZE_CASES(X)                                                                                  \
   X(32) X(36) X(40) X(48) X(64) X(81) X(84) X(96) X(125) X(128) X(160) X(175) X(192) X(243) X(256) X(375) \
   X(384) X(512)
+
+#define PAT_FAST_CASES(X) X(32) X(64) X(128) X(256) X(512)
+
+bool fast_size(int n) { return n == 32 || n == 64 || n == 128 || n == 256 || n == 512; }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -71,6 +77,8 @@ struct TraceScope {
 struct pat_plan {
   pat_grid g;
   int K = 0, m = 0, nh = 0;
+  bool fast = false;         // register-resident power-of-two passes (folded spectra)
+  int nhs = 0;               // spectrum row pitch: nx/2 (fast, folded) or nx/2 + 1
   void* dev = nullptr;       // one allocation for every table
   Tables tb{};
   double* red = nullptr;     // RED_BLOCKS partial sums (misfit)
@@ -100,7 +108,7 @@ Layout make_layout(const pat_plan* p, int ckpt_every) {
   Layout L;
   const pat_grid& g = p->g;
   L.F = (size_t)p->K * g.ny * g.nx * sizeof(float);
-  L.Sp = (size_t)p->K * g.ny * p->nh * sizeof(float2);
+  L.Sp = (size_t)p->K * g.ny * p->nhs * sizeof(float2);
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
@@ -144,9 +152,29 @@ template <int NY>
 int cols_blocks(const pat_plan* p) {
   return p->K * ((p->nh + ColCfg<NY>::TC - 1) / ColCfg<NY>::TC);
 }
+template <int NX>
+int frows_blocks(const pat_plan* p) {
+  return p->K * ((p->g.ny + fast::RowF<NX>::ROWS - 1) / fast::RowF<NX>::ROWS);
+}
+template <int NY>
+int fcols_blocks(const pat_plan* p) {
+  return p->K * ((p->g.nx / 2 + fast::Cfg<NY>::TC - 1) / fast::Cfg<NY>::TC);
+}
 
 int launch_fwd_init(const pat_plan* p, hipStream_t st, const float* c, const float* p0, float* rx, float* ry,
                     float* hist0, float* dpart, float2* SA) {
+  if (p->fast) {
+    switch (p->g.nx) {
+#define X(N)                                                                                              \
+  case N:                                                                                                 \
+    hipLaunchKernelGGL(fast::k_fwd_init<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, p0, rx, ry, \
+                       hist0, dpart, SA);                                                                 \
+    return last_error();
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+  }
   switch (p->g.nx) {
 #define X(N)                                                                                           \
   case N:                                                                                              \
@@ -162,6 +190,17 @@ int launch_fwd_init(const pat_plan* p, hipStream_t st, const float* c, const flo
 
 int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2* SA, float2* SB, int first) {
   TraceScope ts(PAT_PASS_FWD_ROW_U, st);
+  if (p->fast) {
+    switch (p->g.nx) {
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(fast::k_fwd_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, ux, uy, SA, SB, first); \
+    return last_error();
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+  }
   switch (p->g.nx) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
@@ -177,6 +216,18 @@ int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2
 int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx, float* ry, float* hist,
                    float* dpart_n, float2* SA, float2* SB) {
   TraceScope ts(PAT_PASS_FWD_ROW_RHO, st);
+  if (p->fast) {
+    switch (p->g.nx) {
+#define X(N)                                                                                                 \
+  case N:                                                                                                    \
+    hipLaunchKernelGGL(fast::k_fwd_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, rx, ry, hist, \
+                       dpart_n, SA, SB);                                                                     \
+    return last_error();
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+  }
   switch (p->g.nx) {
 #define X(N)                                                                                               \
   case N:                                                                                                  \
@@ -197,6 +248,18 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
                        : MODE == COL_SUMM  ? PAT_PASS_ADJ_COL_SUMM
                                            : PAT_PASS_ADJ_COL_GRAD;
   TraceScope ts(kind, st);
+  if (p->fast) {
+    switch (p->g.ny) {
+#define X(N)                                                                                                     \
+  case N:                                                                                                        \
+    hipLaunchKernelGGL((fast::k_col<N, MODE>), dim3(fcols_blocks<N>(p)), dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), \
+                       0, st, p->tb, SA, SB, scale);                                                             \
+    return last_error();
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+  }
   switch (p->g.ny) {
 #define X(N)                                                                                                 \
   case N:                                                                                                    \
@@ -213,6 +276,18 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
 int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const float* p_n, const float* resid_n,
                    float* rhx, float* rhy, float* gck, float2* SA, float2* SB) {
   TraceScope ts(PAT_PASS_ADJ_ROW_RHO, st);
+  if (p->fast) {
+    switch (p->g.nx) {
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(fast::k_adj_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, p_n, resid_n, \
+                       rhx, rhy, gck, SA, SB);                                                                \
+    return last_error();
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+  }
   switch (p->g.nx) {
 #define X(N)                                                                                                \
   case N:                                                                                                   \
@@ -228,6 +303,17 @@ int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const floa
 
 int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, float2* SA, float2* SB, int final_) {
   TraceScope ts(PAT_PASS_ADJ_ROW_U, st);
+  if (p->fast) {
+    switch (p->g.nx) {
+#define X(N)                                                                                                      \
+  case N:                                                                                                         \
+    hipLaunchKernelGGL(fast::k_adj_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, uhx, uhy, SA, SB, final_); \
+    return last_error();
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+  }
   switch (p->g.nx) {
 #define X(N)                                                                                                     \
   case N:                                                                                                        \
@@ -242,6 +328,18 @@ int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, floa
 
 int launch_adj_final(const pat_plan* p, hipStream_t st, const float* c, const float* p0, const float* resid0,
                      const float* rhx, const float* rhy, float* gck, float* gp0, const float2* SA) {
+  if (p->fast) {
+    switch (p->g.nx) {
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(fast::k_adj_final<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, p0, resid0, \
+                       rhx, rhy, gck, gp0, SA);                                                               \
+    return last_error();
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+  }
   switch (p->g.nx) {
 #define X(N)                                                                                               \
   case N:                                                                                                  \
@@ -446,6 +544,8 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   p->K = K;
   p->m = m;
   p->nh = nh;
+  p->fast = fast_size(nx) && fast_size(ny) && !std::getenv("PAT_GENERIC_KERNELS");
+  p->nhs = p->fast ? nx / 2 : nh;
   if (hipMalloc(&p->dev, total) != hipSuccess) {
     delete p;
     return PAT_EHIP;

@@ -1,0 +1,141 @@
+"""GPU self-consistency of the HIP path (through the C ABI):
+
+* checkpointed history (recompute from checkpoints) gives bit-identical
+  gradients to the stored history, including a ragged last segment;
+* a batch of K datasets gives bit-identical data and g_p0 to K single runs,
+  and g_c equal to their sum in the same order;
+* oracle parity at 512^2 on a short time axis, and the W1 launch
+  configuration (512^2, K = 8, 4000 samples) checked by properties that hold
+  at any size: linearity in p0 and the adjoint dot-product identity;
+* the generic (any radix) kernels and the power-of-two kernels agree.
+"""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+from paper_2505_08482_amd import inputs as I
+from gpu_helpers import announce, gpu_forward_adjoint, oracle_forward_adjoint, observed_data, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _wl(n=128, K=3, nt=203, m=96):
+    g = I.make_grid(n, 1e-4 * 256 / n, nt, 10)
+    rs = round(0.38 * n)
+    return I.Workload(f"c_{n}_K{K}_nt{nt}", g, K=K, m=m, sensor_radius_px=float(rs),
+                      support_radius_px=float(rs - 4))
+
+
+def _inputs(wl, seed=0):
+    c, p0 = I.phantoms(wl, 2, case=seed)
+    rng = np.random.default_rng(seed + 11)
+    resid = rng.standard_normal((wl.K, wl.grid.nt, wl.m)).astype(np.float32)
+    return c.astype(np.float32), p0.astype(np.float32), resid
+
+
+@pytest.mark.parametrize("s", [16, 50, 7])
+def test_checkpointed_equals_store_all_bitwise(s):
+    wl = _wl()
+    c, p0, r = _inputs(wl)
+    announce(f"store-all vs ckpt s={s}")
+    a = gpu_forward_adjoint(wl, c, p0, resid32=r, ckpt_every=0)
+    b = gpu_forward_adjoint(wl, c, p0, resid32=r, ckpt_every=s)
+    assert np.array_equal(a["data"], b["data"])
+    assert np.array_equal(a["g_p0"], b["g_p0"])
+    assert np.array_equal(a["g_c"], b["g_c"])
+
+
+def test_batch_equals_single_runs_bitwise():
+    wl = _wl(K=4, nt=150)
+    c, p0, r = _inputs(wl, seed=3)
+    announce("batch K=4 vs singles")
+    full = gpu_forward_adjoint(wl, c, p0, resid32=r)
+    gc_sum = np.zeros_like(full["g_c"])
+    for k in range(wl.K):
+        w1 = dataclasses.replace(wl, K=1)
+        one = gpu_forward_adjoint(w1, c, p0[k:k + 1], resid32=np.ascontiguousarray(r[k:k + 1]))
+        assert np.array_equal(one["data"][0], full["data"][k])
+        assert np.array_equal(one["g_p0"][0], full["g_p0"][k])
+        gc_sum = (gc_sum + one["g_c"]).astype(np.float32)
+    assert np.array_equal(gc_sum, full["g_c"])
+
+
+def test_oracle_parity_512_short():
+    wl = I.w1(K=1, nt=150)
+    c_true, p0 = I.phantoms(wl, 3)
+    c_true = c_true.astype(np.float32)
+    p0 = p0.astype(np.float32)
+    y, w = observed_data(wl, c_true, p0, noise_seed=3500)
+    c = np.full_like(c_true, np.float32(1500.0))
+    announce("512 K=1 nt=150 oracle")
+    ora = oracle_forward_adjoint(wl, c, p0, y=y, w=w)
+    announce("512 K=1 nt=150 gpu")
+    gpu = gpu_forward_adjoint(wl, c, p0, resid32=ora["resid"].astype(np.float32))
+    e = (rel_l2(gpu["data"], ora["data"]), rel_l2(gpu["g_p0"], ora["g_p0"]), rel_l2(gpu["g_c"], ora["g_c"]))
+    print(f"[parity] 512 short: {e}", flush=True)
+    assert e[0] <= 1e-4 and e[1] <= 1e-3 and e[2] <= 1e-3
+
+
+def test_w1_full_size_properties():
+    """512^2, K = 8, 4000 samples (the benchmark's launch configuration):
+    f(a + 2b) = f(a) + 2 f(b) and <f(p0), y> = <p0, f^T y> in float32."""
+    import torch
+    from paper_2505_08482_amd import pat
+    wl = I.w1()
+    g = wl.grid
+    c_np, p0_np = I.phantoms(wl, 3)
+    plan = pat.Plan(g, wl.K, wl.sensors)
+    ws = plan.workspace(0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    c = T(c_np)
+    rng = np.random.default_rng(9)
+    a = T(p0_np)
+    b = T(rng.uniform(0, 1, p0_np.shape) * (p0_np > 0.01))
+    ab = a + 2.0 * b
+    out = {}
+    announce("w1 full-size forward x3")
+    for name, p in (("a", a), ("b", b), ("ab", ab)):
+        d = torch.empty(plan.data_shape, dtype=torch.float32, device="cuda")
+        plan.forward(c, p, d, ws, record=False)
+        out[name] = d
+    lin = rel_l2((out["a"] + 2.0 * out["b"]).cpu().numpy(), out["ab"].cpu().numpy())
+    print(f"[w1] linearity rel {lin:.2e}", flush=True)
+    assert lin < 1e-5
+    y = T(rng.standard_normal(plan.data_shape))
+    d = torch.empty(plan.data_shape, dtype=torch.float32, device="cuda")
+    announce("w1 full-size forward+adjoint")
+    plan.forward(c, a, d, ws, record=True)
+    gp0 = torch.empty(plan.field_shape, dtype=torch.float32, device="cuda")
+    gc = torch.empty((g.ny, g.nx), dtype=torch.float32, device="cuda")
+    plan.adjoint_gradient(c, a, y, gp0, gc, ws)
+    lhs = float((d.double() * y.double()).sum())
+    rhs = float((a.double() * gp0.double()).sum())
+    print(f"[w1] dot test {lhs:.6e} {rhs:.6e} rel {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+    assert torch.isfinite(gc).all()
+    plan.close()
+
+
+def test_generic_and_power_of_two_kernels_agree():
+    """The same 128^2 problem through both kernel families agrees to float32
+    rounding (the family is fixed when a plan is created: PAT_GENERIC_KERNELS
+    set -> the any-radix kernels)."""
+    wl = _wl(K=2, nt=120)
+    c, p0, r = _inputs(wl, seed=5)
+    outs = []
+    try:
+        for generic in (False, True):
+            if generic:
+                os.environ["PAT_GENERIC_KERNELS"] = "1"
+            else:
+                os.environ.pop("PAT_GENERIC_KERNELS", None)
+            announce(f"kernel family generic={generic}")
+            outs.append(gpu_forward_adjoint(wl, c, p0, resid32=r))
+    finally:
+        os.environ.pop("PAT_GENERIC_KERNELS", None)
+    for key in ("data", "g_p0", "g_c"):
+        e = rel_l2(outs[0][key], outs[1][key])
+        print(f"[families] {key} {e:.2e}", flush=True)
+        assert e < 1e-5, (key, e)
