@@ -35,9 +35,17 @@ template <> struct Cfg<64>  { static constexpr int T = 8;  using L = RList<8, 8>
 template <> struct Cfg<32>  { static constexpr int T = 4;  using L = RList<8, 4>;    static constexpr int TC = 64; };
 
 // LDS position of element i: one pad slot per 8 keeps the radix-8 exchanges
-// (stride-8 writes, stride-1 reads) free of bank conflicts.
+// (stride-8 writes, stride-1 reads) free of bank conflicts within a transform.
 __device__ __forceinline__ int phys(int i) { return i + (i >> 3); }
-template <int N> struct Lds { static constexpr int P = N + N / 8 + 8; };   // pitch of one transform
+// Pitch of one transform.  Row passes: one transform per lane group.  Column
+// passes interleave TC columns across the lanes of a wave: a pitch of 2 (mod 16)
+// complex spreads 8 columns x 2 rows of a 16-lane group over all 32 banks, an
+// odd pitch spreads 16 columns.
+template <int N> struct Lds { static constexpr int P = N + N / 8 + 2; };
+template <int N> struct LdsCol {
+  static constexpr int base = N + N / 8;
+  static constexpr int P = Cfg<N>::TC == 8 ? base + ((18 - base % 16) % 16) : (base | 1);
+};
 
 // One register-resident Stockham stage on NV transforms at once (shared barriers).
 template <int N, int T, int R, int NS, int DIR, bool LAST, int NV>
@@ -243,11 +251,13 @@ __global__ __launch_bounds__(64) void k_fwd_init(Tables tb, const float* __restr
   if (y1 < ny) unpack_store<N>(v[0], q, lane_base, ra, rb);
 }
 
-// velocity update (first != 0: u^{-1/2} = G/2), spectra of (u_x + i u_y)
+// velocity update (step 0: u^{-1/2} = G/2), spectra of (u_x + i u_y)
 template <int N>
 __global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux, float* __restrict__ uy,
-                                              float2* __restrict__ SA, float2* __restrict__ SB, int first) {
+                                              float2* __restrict__ SA, float2* __restrict__ SB,
+                                              const StepCtl* __restrict__ ctl) {
   PAT_ROW_PROLOGUE(N)
+  const int first = ctl->fwd_n == 0;
   __shared__ float2 X[RC::G][2][Lds<N>::P];
   float2 v[2][8];
   float ox[2][8], oy[2][8];
@@ -303,10 +313,13 @@ __global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux,
 // density / pressure update, history, sensors at n+1, spectra of p (rows y0, y1 share one FFT)
 template <int N>
 __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restrict__ c, float* __restrict__ rx,
-                                                float* __restrict__ ry, float* __restrict__ hist,
-                                                float* __restrict__ dpart_n, float2* __restrict__ SA,
-                                                const float2* __restrict__ SB) {
+                                                float* __restrict__ ry, float* __restrict__ hist_base,
+                                                float* __restrict__ dpart, float2* __restrict__ SA,
+                                                const float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   PAT_ROW_PROLOGUE(N)
+  const int n = ctl->fwd_n;
+  float* hist = hist_base ? hist_base + (size_t)(n + 1 - ctl->hist_first) * tb.K * ny * N : nullptr;
+  float* dpart_n = dpart ? dpart + (size_t)(n + 1) * 2 * tb.m : nullptr;
   __shared__ float2 X[RC::G][2][Lds<N>::P];
   __shared__ float P[RC::ROWS][N];
   float2 v[2][8];
@@ -327,6 +340,11 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
       cc[h][m] = c[(size_t)y * N + x];
     }
   }
+  // sensor taps of this block's rows (one entry per thread, prefetched)
+  const int g0 = tb.g_row_start[ybase], g1 = tb.g_row_start[min(ybase + RC::ROWS, ny)];
+  GatherEnt ge{};
+  const bool has_g = dpart_n && (g0 + tid < g1);
+  if (has_g) ge = tb.g_ent[g0 + tid];
   float2* L[2] = {X[grp][0], X[grp][1]};
   fft.template run<+1, 2>(v, L, q);
   float2 z[1][8];
@@ -353,7 +371,18 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
     }
   }
   __syncthreads();
-  if (dpart_n) gather_rows<N, 64>(tb, &P[0][0], ybase, RC::ROWS, dpart_n + (size_t)k * tb.nt * 2 * tb.m, tid);
+  if (dpart_n) {
+    float* dk = dpart_n + (size_t)k * tb.nt * 2 * tb.m;
+    if (has_g) {
+      const float* pr = &P[ge.row - ybase][0];
+      dk[ge.slot * tb.m + ge.sensor] = ge.w0 * pr[ge.ix0] + ge.w1 * pr[ge.ix0 + 1];
+    }
+    for (int e2 = g0 + 64 + tid; e2 < g1; e2 += 64) {
+      const GatherEnt g = tb.g_ent[e2];
+      const float* pr = &P[g.row - ybase][0];
+      dk[g.slot * tb.m + g.sensor] = g.w0 * pr[g.ix0] + g.w1 * pr[g.ix0 + 1];
+    }
+  }
   float2* L1[1] = {X[grp][0]};
   fft.template run<-1, 1>(z, L1, q);
   if (ok) {
@@ -365,21 +394,56 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
 
 // adjoint: ph = S^T r^n + (inverse rows of the SUMM spectrum); rh += c^2 ph;
 // gc += (2/c) p^n ph; spectra of (a_x rh_x + i a_y rh_y); rh <- a^2 rh.
+// Every global load (spectra, state, history, sensor injections) is issued
+// before the first transform so that their latencies overlap.
 template <int N>
-__global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restrict__ c, const float* __restrict__ p_n,
-                                                const float* __restrict__ resid_n, float* __restrict__ rhx,
-                                                float* __restrict__ rhy, float* __restrict__ gck,
-                                                float2* __restrict__ SA, float2* __restrict__ SB) {
+__global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restrict__ c,
+                                                const float* __restrict__ hist_base, const float* __restrict__ resid,
+                                                float* __restrict__ rhx, float* __restrict__ rhy,
+                                                float* __restrict__ gck, float2* __restrict__ SA,
+                                                float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   PAT_ROW_PROLOGUE(N)
+  const int n = ctl->adj_n;
+  const float* p_n = hist_base + (size_t)(n - ctl->hist_first) * tb.K * ny * N;
+  const float* resid_n = resid + (size_t)n * tb.m;
   __shared__ float2 X[RC::G][2][Lds<N>::P];
   __shared__ float PH[RC::ROWS][N];
   const bool ok = y1 < ny;
   float2 v[1][8];
+  float orx[2][8], ory[2][8], og[2][8], op[2][8], oc[2][8];
   {
     const float2* A = SA + ((size_t)k * ny + (ok ? y0 : 0)) * nhf;
     const float2* B = SA + ((size_t)k * ny + (ok ? y1 : 0)) * nhf;
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[0][m] = pack_folded(A, B, q + T * m, N);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const size_t f = ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int x = q + T * m;
+      orx[h][m] = rhx[f + x];
+      ory[h][m] = rhy[f + x];
+      og[h][m] = gck[f + x];
+      op[h][m] = p_n[f + x];
+      oc[h][m] = c[(size_t)y * N + x];
+    }
+  }
+  // sensor injections of this block's rows: one pixel per thread (prefetched)
+  const float* rk = resid_n + (size_t)k * tb.nt * tb.m;
+  const int e0 = tb.s_row_start[ybase], e1 = tb.s_row_start[min(ybase + RC::ROWS, ny)];
+  const int e = e0 + tid;
+  float inj = 0.f;
+  int inj_at = -1;
+  if (e < e1) {
+    const ScatterPix px = tb.s_pix[e];
+    for (int t = 0; t < px.count; ++t) {
+      const ScatterTap tp = tb.s_tap[px.start + t];
+      inj += tp.w * rk[tp.sensor];
+    }
+    inj_at = (px.row - ybase) * N + px.ix;
   }
   float2* L1[1] = {X[grp][0]};
   fft.template run<+1, 1>(v, L1, q);
@@ -389,7 +453,18 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
     PH[2 * grp + 1][q + T * m] = v[0][m].y;
   }
   __syncthreads();
-  scatter_rows<N, 64>(tb, &PH[0][0], ybase, RC::ROWS, resid_n + (size_t)k * tb.nt * tb.m, tid);
+  if (inj_at >= 0) (&PH[0][0])[inj_at] += inj;
+  if (e1 - e0 > 64) {   // rows crowded with sensors: the remaining pixels, one pass each
+    for (int e2 = e0 + 64 + tid; e2 < e1; e2 += 64) {
+      const ScatterPix px = tb.s_pix[e2];
+      float acc = 0.f;
+      for (int t = 0; t < px.count; ++t) {
+        const ScatterTap tp = tb.s_tap[px.start + t];
+        acc += tp.w * rk[tp.sensor];
+      }
+      (&PH[0][0])[(px.row - ybase) * N + px.ix] += acc;
+    }
+  }
   __syncthreads();
   float2 w[2][8];
 #pragma unroll
@@ -401,11 +476,11 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
     for (int m = 0; m < 8; ++m) {
       const int x = q + T * m;
       const float ph = PH[2 * grp + h][x];
-      const float cv = c[(size_t)y * N + x];
+      const float cv = oc[h][m];
       const float c2 = cv * cv;
-      const float nrx = rhx[f + x] + c2 * ph;
-      const float nry = rhy[f + x] + c2 * ph;
-      const float gnew = gck[f + x] + (2.0f / cv) * p_n[f + x] * ph;
+      const float nrx = orx[h][m] + c2 * ph;
+      const float nry = ory[h][m] + c2 * ph;
+      const float gnew = og[h][m] + (2.0f / cv) * op[h][m] * ph;
       if (ok) {
         gck[f + x] = gnew;
         rhx[f + x] = tb.ax2[x] * nrx;
@@ -426,11 +501,13 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
 }
 
 // adjoint velocities: uh <- as^2 uh + (inverse rows of PAIRP spectra);
-// spectra of (w_x uh_x + i w_y uh_y), w = as or as - as^2/2 (final != 0)
+// spectra of (w_x uh_x + i w_y uh_y), w = as, or as - as^2/2 at adjoint step n = 1
 template <int N>
 __global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx, float* __restrict__ uhy,
-                                              float2* __restrict__ SA, float2* __restrict__ SB, int final_) {
+                                              float2* __restrict__ SA, float2* __restrict__ SB,
+                                              const StepCtl* __restrict__ ctl) {
   PAT_ROW_PROLOGUE(N)
+  const int final_ = ctl->adj_n == 1;
   __shared__ float2 X[RC::G][2][Lds<N>::P];
   float2 v[2][8];
   float ox[2][8], oy[2][8];
@@ -529,8 +606,11 @@ __global__ __launch_bounds__(64) void k_adj_final(Tables tb, const float* __rest
 // ===========================================================================
 template <int N, int MODE>
 __global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
-                                                                float2* __restrict__ SB, float scale) {
-  constexpr int T = Cfg<N>::T, TC = Cfg<N>::TC, P = Lds<N>::P;
+                                                                float2* __restrict__ SB, float scale,
+                                                                int32_t* __restrict__ step, int32_t delta) {
+  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;   // first pass of a step
+  constexpr int T = Cfg<N>::T, TC = Cfg<N>::TC, P = LdsCol<N>::P;
+  static_assert(TC != 8 || P % 16 == 2, "column pitch");
   constexpr bool TWO_IN = MODE != COL_GRAD1;
   constexpr bool TWO_OUT = MODE != COL_SUMM;
   __shared__ float2 LA[TC * P];

@@ -88,12 +88,22 @@ struct pat_plan {
   const float* rec_c = nullptr;
   const float* rec_p0 = nullptr;
   int rec_ckpt = 0;
+  // captured step-chunk graphs (replayed while their launch arguments repeat)
+  struct GraphEntry {
+    uint64_t key[14];
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t cap = nullptr;   // private stream for capture (the caller's may be the null stream)
 };
 
 namespace {
 
 struct Layout {
   size_t F = 0, Sp = 0;           // bytes of one [K][ny][nx] field / one [K][ny][nh] spectrum
+  size_t ctl;                     // StepCtl
   size_t ux, uy, rx, ry;          // forward state
   size_t uhx, uhy, rhx, rhy, gck; // adjoint state
   size_t SA, SB, SC, SD;          // spectra (forward pair, adjoint pair)
@@ -115,6 +125,7 @@ Layout make_layout(const pat_plan* p, int ckpt_every) {
     off += align256(b);
     return o;
   };
+  L.ctl = take(sizeof(StepCtl));
   L.ux = take(L.F); L.uy = take(L.F); L.rx = take(L.F); L.ry = take(L.F);
   L.uhx = take(L.F); L.uhy = take(L.F); L.rhx = take(L.F); L.rhy = take(L.F); L.gck = take(L.F);
   L.SA = take(L.Sp); L.SB = take(L.Sp); L.SC = take(L.Sp); L.SD = take(L.Sp);
@@ -188,13 +199,14 @@ int launch_fwd_init(const pat_plan* p, hipStream_t st, const float* c, const flo
   return last_error();
 }
 
-int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2* SA, float2* SB, int first) {
+int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2* SA, float2* SB,
+                 const StepCtl* ctl) {
   TraceScope ts(PAT_PASS_FWD_ROW_U, st);
   if (p->fast) {
     switch (p->g.nx) {
-#define X(N)                                                                                                  \
-  case N:                                                                                                     \
-    hipLaunchKernelGGL(fast::k_fwd_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, ux, uy, SA, SB, first); \
+#define X(N)                                                                                                \
+  case N:                                                                                                   \
+    hipLaunchKernelGGL(fast::k_fwd_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, ux, uy, SA, SB, ctl); \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -202,9 +214,9 @@ int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2
     }
   }
   switch (p->g.nx) {
-#define X(N)                                                                                                  \
-  case N:                                                                                                     \
-    hipLaunchKernelGGL(k_fwd_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, ux, uy, SA, SB, first); \
+#define X(N)                                                                                                \
+  case N:                                                                                                   \
+    hipLaunchKernelGGL(k_fwd_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, ux, uy, SA, SB, ctl); \
     break;
     PAT_SIZE_CASES(X)
 #undef X
@@ -213,15 +225,15 @@ int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2
   return last_error();
 }
 
-int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx, float* ry, float* hist,
-                   float* dpart_n, float2* SA, float2* SB) {
+int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx, float* ry, float* hist_base,
+                   float* dpart, float2* SA, float2* SB, const StepCtl* ctl) {
   TraceScope ts(PAT_PASS_FWD_ROW_RHO, st);
   if (p->fast) {
     switch (p->g.nx) {
-#define X(N)                                                                                                 \
-  case N:                                                                                                    \
-    hipLaunchKernelGGL(fast::k_fwd_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, rx, ry, hist, \
-                       dpart_n, SA, SB);                                                                     \
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(fast::k_fwd_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, rx, ry,       \
+                       hist_base, dpart, SA, SB, ctl);                                                        \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -229,10 +241,10 @@ int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx,
     }
   }
   switch (p->g.nx) {
-#define X(N)                                                                                               \
-  case N:                                                                                                  \
-    hipLaunchKernelGGL(k_fwd_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, rx, ry, hist, \
-                       dpart_n, SA, SB);                                                                   \
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(k_fwd_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, rx, ry, hist_base, \
+                       dpart, SA, SB, ctl);                                                                   \
     break;
     PAT_SIZE_CASES(X)
 #undef X
@@ -241,8 +253,10 @@ int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx,
   return last_error();
 }
 
+// step != nullptr: this launch is the first pass of a step and advances *step by delta
 template <int MODE>
-int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float scale) {
+int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float scale, int32_t* step,
+               int32_t delta) {
   constexpr int kind = MODE == COL_GRAD1 ? PAT_PASS_FWD_COL_GRAD
                        : MODE == COL_PAIRM ? PAT_PASS_FWD_COL_DIV
                        : MODE == COL_SUMM  ? PAT_PASS_ADJ_COL_SUMM
@@ -253,7 +267,7 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
 #define X(N)                                                                                                     \
   case N:                                                                                                        \
     hipLaunchKernelGGL((fast::k_col<N, MODE>), dim3(fcols_blocks<N>(p)), dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), \
-                       0, st, p->tb, SA, SB, scale);                                                             \
+                       0, st, p->tb, SA, SB, scale, step, delta);                                                \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -264,7 +278,7 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
 #define X(N)                                                                                                 \
   case N:                                                                                                    \
     hipLaunchKernelGGL((k_col<N, MODE>), dim3(cols_blocks<N>(p)), dim3(ColCfg<N>::BLOCK), 0, st, p->tb, SA, \
-                       SB, scale);                                                                           \
+                       SB, scale, step, delta);                                                              \
     break;
     PAT_SIZE_CASES(X)
 #undef X
@@ -273,15 +287,15 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
   return last_error();
 }
 
-int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const float* p_n, const float* resid_n,
-                   float* rhx, float* rhy, float* gck, float2* SA, float2* SB) {
+int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const float* hist_base, const float* resid,
+                   float* rhx, float* rhy, float* gck, float2* SA, float2* SB, const StepCtl* ctl) {
   TraceScope ts(PAT_PASS_ADJ_ROW_RHO, st);
   if (p->fast) {
     switch (p->g.nx) {
-#define X(N)                                                                                                  \
-  case N:                                                                                                     \
-    hipLaunchKernelGGL(fast::k_adj_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, p_n, resid_n, \
-                       rhx, rhy, gck, SA, SB);                                                                \
+#define X(N)                                                                                                   \
+  case N:                                                                                                      \
+    hipLaunchKernelGGL(fast::k_adj_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, hist_base,     \
+                       resid, rhx, rhy, gck, SA, SB, ctl);                                                     \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -289,10 +303,10 @@ int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const floa
     }
   }
   switch (p->g.nx) {
-#define X(N)                                                                                                \
-  case N:                                                                                                   \
-    hipLaunchKernelGGL(k_adj_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, p_n, resid_n, rhx, \
-                       rhy, gck, SA, SB);                                                                   \
+#define X(N)                                                                                                    \
+  case N:                                                                                                       \
+    hipLaunchKernelGGL(k_adj_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, hist_base, resid, rhx, \
+                       rhy, gck, SA, SB, ctl);                                                                  \
     break;
     PAT_SIZE_CASES(X)
 #undef X
@@ -301,13 +315,14 @@ int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const floa
   return last_error();
 }
 
-int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, float2* SA, float2* SB, int final_) {
+int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, float2* SA, float2* SB,
+                 const StepCtl* ctl) {
   TraceScope ts(PAT_PASS_ADJ_ROW_U, st);
   if (p->fast) {
     switch (p->g.nx) {
-#define X(N)                                                                                                      \
-  case N:                                                                                                         \
-    hipLaunchKernelGGL(fast::k_adj_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, uhx, uhy, SA, SB, final_); \
+#define X(N)                                                                                                    \
+  case N:                                                                                                       \
+    hipLaunchKernelGGL(fast::k_adj_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, uhx, uhy, SA, SB, ctl); \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -315,9 +330,9 @@ int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, floa
     }
   }
   switch (p->g.nx) {
-#define X(N)                                                                                                     \
-  case N:                                                                                                        \
-    hipLaunchKernelGGL(k_adj_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, uhx, uhy, SA, SB, final_); \
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(k_adj_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, uhx, uhy, SA, SB, ctl); \
     break;
     PAT_SIZE_CASES(X)
 #undef X
@@ -366,23 +381,110 @@ int copy_dev(hipStream_t st, const void* src, void* dst, size_t bytes) {
   return last_error();
 }
 
-#define PAT_TRY(expr)          \
-  do {                         \
-    int _s = (expr);           \
+int set_ctl(hipStream_t st, StepCtl* ctl, int mask, int fwd_n, int adj_n, int hist_first) {
+  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(1), 0, st, reinterpret_cast<int32_t*>(ctl), mask, fwd_n, adj_n,
+                     hist_first);
+  return last_error();
+}
+
+#define PAT_TRY(expr)            \
+  do {                           \
+    int _s = (expr);             \
     if (_s != PAT_OK) return _s; \
   } while (0)
 
-// One forward update n -> n+1 (four passes).
-int forward_step(const pat_plan* p, hipStream_t st, const float* c, float* ux, float* uy, float* rx, float* ry,
-                 float2* SA, float2* SB, int n, float* hist_next, float* dpart_next) {
+// Arguments of a run of time steps (identical for every step of the run).
+struct FwdArgs {
+  const float* c;
+  float *ux, *uy, *rx, *ry;
+  float2 *SA, *SB;
+  float* hist_base;   // nullptr: no history
+  float* dpart;       // nullptr: no sensor samples
+  StepCtl* ctl;
+};
+struct AdjArgs {
+  const float* c;
+  const float* hist_base;
+  const float* resid;
+  float *uhx, *uhy, *rhx, *rhy, *gck;
+  float2 *SC, *SD;
+  StepCtl* ctl;
+};
+
+int fwd_steps(const pat_plan* p, hipStream_t st, const FwdArgs& a, int count) {
   const pat_grid& g = p->g;
   const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
-  PAT_TRY(launch_col<COL_GRAD1>(p, st, SA, SB, (float)(g.dt / g.rho0 * nrm)));
-  PAT_TRY(launch_fwd_u(p, st, ux, uy, SA, SB, n == 0 ? 1 : 0));
-  PAT_TRY(launch_col<COL_PAIRM>(p, st, SA, SB, (float)(g.dt * g.rho0 * nrm)));
-  PAT_TRY(launch_fwd_rho(p, st, c, rx, ry, hist_next, dpart_next, SA, SB));
+  for (int i = 0; i < count; ++i) {
+    PAT_TRY(launch_col<COL_GRAD1>(p, st, a.SA, a.SB, (float)(g.dt / g.rho0 * nrm), &a.ctl->fwd_n, +1));
+    PAT_TRY(launch_fwd_u(p, st, a.ux, a.uy, a.SA, a.SB, a.ctl));
+    PAT_TRY(launch_col<COL_PAIRM>(p, st, a.SA, a.SB, (float)(g.dt * g.rho0 * nrm), nullptr, 0));
+    PAT_TRY(launch_fwd_rho(p, st, a.c, a.rx, a.ry, a.hist_base, a.dpart, a.SA, a.SB, a.ctl));
+  }
   return PAT_OK;
 }
+
+int adj_steps(const pat_plan* p, hipStream_t st, const AdjArgs& a, int count) {
+  const pat_grid& g = p->g;
+  const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
+  for (int i = 0; i < count; ++i) {
+    PAT_TRY(launch_col<COL_SUMM>(p, st, a.SC, a.SD, (float)(g.dt / g.rho0 * nrm), &a.ctl->adj_n, -1));
+    PAT_TRY(launch_adj_rho(p, st, a.c, a.hist_base, a.resid, a.rhx, a.rhy, a.gck, a.SC, a.SD, a.ctl));
+    PAT_TRY(launch_col<COL_PAIRP>(p, st, a.SC, a.SD, (float)(g.dt * g.rho0 * nrm), nullptr, 0));
+    PAT_TRY(launch_adj_u(p, st, a.uhx, a.uhy, a.SC, a.SD, a.ctl));
+  }
+  return PAT_OK;
+}
+
+bool graphs_enabled() { return !g_trace.on && !std::getenv("PAT_NO_GRAPHS"); }
+
+// Enqueue `count` steps on `st`: replay a captured graph when the same run
+// (kind, arguments, count) was captured before, else capture it on the plan's
+// private stream first.  Runs of one step are launched directly.
+template <typename Args, typename Body>
+int run_steps(pat_plan* p, hipStream_t st, const Args& a, int count, uint64_t kind, Body body) {
+  if (count <= 0) return PAT_OK;
+  if (count == 1 || !graphs_enabled()) return body(p, st, a, count);
+  uint64_t key[14] = {kind, (uint64_t)count};
+  static_assert(sizeof(Args) <= 12 * sizeof(uint64_t), "graph key");
+  std::memcpy(&key[2], &a, sizeof(Args));
+  for (auto& e : p->graphs) {
+    if (std::memcmp(e.key, key, sizeof(key)) == 0) {
+      e.last_use = ++p->graph_clock;
+      return hipGraphLaunch(e.exec, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+    }
+  }
+  if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) return PAT_EHIP;
+  // the capture stream must not run ahead of work already queued on st
+  if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PAT_EHIP;
+  const int st_body = body(p, p->cap, a, count);
+  hipGraph_t graph = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(p->cap, &graph);
+  if (st_body != PAT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st_body;
+  }
+  if (e_end != hipSuccess || !graph) return PAT_EHIP;
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e_inst != hipSuccess) return PAT_EHIP;
+  if (p->graphs.size() >= 8) {   // evict the least recently used
+    auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                [](const pat_plan::GraphEntry& x, const pat_plan::GraphEntry& y) {
+                                  return x.last_use < y.last_use;
+                                });
+    (void)hipGraphExecDestroy(lru->exec);
+    p->graphs.erase(lru);
+  }
+  pat_plan::GraphEntry ent;
+  std::memcpy(ent.key, key, sizeof(key));
+  ent.exec = exec;
+  ent.last_use = ++p->graph_clock;
+  p->graphs.push_back(ent);
+  return hipGraphLaunch(exec, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+constexpr int kChunk = 32;   // time steps per captured graph in store-all runs
 
 // ----------------------------------------------------------------------------
 // Host-side tables
@@ -580,6 +682,9 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
 
 int pat_plan_destroy(pat_plan* p) {
   if (!p) return PAT_EINVAL;
+  for (auto& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
+  p->graphs.clear();
+  if (p->cap) (void)hipStreamDestroy(p->cap);
   if (p->dev) (void)hipFree(p->dev);
   delete p;
   return PAT_OK;
@@ -598,30 +703,39 @@ int pat_forward(pat_plan* p, const float* c, const float* p0, float* data, void*
   if (ws_bytes < L.total) return PAT_EWORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const pat_grid& g = p->g;
-  float *ux = at<float>(ws, L.ux), *uy = at<float>(ws, L.uy), *rx = at<float>(ws, L.rx), *ry = at<float>(ws, L.ry);
-  float2 *SA = at<float2>(ws, L.SA), *SB = at<float2>(ws, L.SB);
-  float* dpart = at<float>(ws, L.dpart);
-  const size_t fl = L.F / sizeof(float);
+  FwdArgs a;
+  a.c = c;
+  a.ux = at<float>(ws, L.ux); a.uy = at<float>(ws, L.uy); a.rx = at<float>(ws, L.rx); a.ry = at<float>(ws, L.ry);
+  a.SA = at<float2>(ws, L.SA); a.SB = at<float2>(ws, L.SB);
+  a.dpart = at<float>(ws, L.dpart);
+  a.ctl = at<StepCtl>(ws, L.ctl);
   const bool store_all = record && ckpt_every == 0;
-  float* hist = store_all ? at<float>(ws, L.hist) : nullptr;
+  const bool ckpt = record && ckpt_every > 0;
+  a.hist_base = store_all ? at<float>(ws, L.hist) : nullptr;
   if (record) p->recorded = false;
+  auto body = [](pat_plan* pp, hipStream_t s2, const FwdArgs& aa, int cnt) { return fwd_steps(pp, s2, aa, cnt); };
 
-  PAT_TRY(launch_fwd_init(p, st, c, p0, rx, ry, hist, dpart, SA));
-  for (int n = 0; n + 1 < g.nt; ++n) {
-    if (record && ckpt_every > 0 && n > 0 && n % ckpt_every == 0) {
+  PAT_TRY(set_ctl(st, a.ctl, 1 | 4, -1, 0, 0));
+  PAT_TRY(launch_fwd_init(p, st, c, p0, a.rx, a.ry, a.hist_base, a.dpart, a.SA));
+  const int steps = g.nt - 1;
+  int n = 0;
+  while (n < steps) {
+    if (ckpt && n > 0 && n % ckpt_every == 0) {
       const int slot = n / ckpt_every - 1;
       char* ck = at<char>(ws, L.ckpt) + (size_t)slot * (4 * align256(L.F) + align256(L.Sp));
-      PAT_TRY(copy_dev(st, ux, ck, L.F));
-      PAT_TRY(copy_dev(st, uy, ck + align256(L.F), L.F));
-      PAT_TRY(copy_dev(st, rx, ck + 2 * align256(L.F), L.F));
-      PAT_TRY(copy_dev(st, ry, ck + 3 * align256(L.F), L.F));
-      PAT_TRY(copy_dev(st, SA, ck + 4 * align256(L.F), L.Sp));
+      PAT_TRY(copy_dev(st, a.ux, ck, L.F));
+      PAT_TRY(copy_dev(st, a.uy, ck + align256(L.F), L.F));
+      PAT_TRY(copy_dev(st, a.rx, ck + 2 * align256(L.F), L.F));
+      PAT_TRY(copy_dev(st, a.ry, ck + 3 * align256(L.F), L.F));
+      PAT_TRY(copy_dev(st, a.SA, ck + 4 * align256(L.F), L.Sp));
     }
-    PAT_TRY(forward_step(p, st, c, ux, uy, rx, ry, SA, SB, n, hist ? hist + (size_t)(n + 1) * fl : nullptr,
-                         dpart + (size_t)(n + 1) * 2 * p->m));
+    int cnt = std::min(kChunk, steps - n);
+    if (ckpt) cnt = std::min(ckpt_every - n % ckpt_every, steps - n);
+    PAT_TRY(run_steps(p, st, a, cnt, 1, body));
+    n += cnt;
   }
   const int64_t rows = (int64_t)p->K * g.nt;
-  hipLaunchKernelGGL(k_sensor_finalize, dim3(grid_blocks(rows * p->m)), dim3(256), 0, st, dpart, data, rows, p->m);
+  hipLaunchKernelGGL(k_sensor_finalize, dim3(grid_blocks(rows * p->m)), dim3(256), 0, st, a.dpart, data, rows, p->m);
   PAT_TRY(last_error());
   if (record) {
     p->recorded = true;
@@ -654,58 +768,65 @@ int pat_adjoint_gradient(pat_plan* p, const float* c, const float* p0, const flo
   hipStream_t st = static_cast<hipStream_t>(stream);
   const pat_grid& g = p->g;
   const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
-  const size_t fl = L.F / sizeof(float);
-  float *uhx = at<float>(ws, L.uhx), *uhy = at<float>(ws, L.uhy), *rhx = at<float>(ws, L.rhx),
-        *rhy = at<float>(ws, L.rhy), *gck = at<float>(ws, L.gck);
-  float2 *SC = at<float2>(ws, L.SC), *SD = at<float2>(ws, L.SD);
-  float* hist = at<float>(ws, L.hist);
+  AdjArgs a;
+  a.c = c;
+  a.hist_base = at<float>(ws, L.hist);
+  a.resid = resid;
+  a.uhx = at<float>(ws, L.uhx); a.uhy = at<float>(ws, L.uhy); a.rhx = at<float>(ws, L.rhx);
+  a.rhy = at<float>(ws, L.rhy); a.gck = at<float>(ws, L.gck);
+  a.SC = at<float2>(ws, L.SC); a.SD = at<float2>(ws, L.SD);
+  a.ctl = at<StepCtl>(ws, L.ctl);
+  auto abody = [](pat_plan* pp, hipStream_t s2, const AdjArgs& aa, int cnt) { return adj_steps(pp, s2, aa, cnt); };
+  auto fbody = [](pat_plan* pp, hipStream_t s2, const FwdArgs& aa, int cnt) { return fwd_steps(pp, s2, aa, cnt); };
   // adjoint state starts at zero (fill kernels: no memset nodes)
-  PAT_TRY(fill_zero(st, uhx, L.F));
-  PAT_TRY(fill_zero(st, uhy, L.F));
-  PAT_TRY(fill_zero(st, rhx, L.F));
-  PAT_TRY(fill_zero(st, rhy, L.F));
-  PAT_TRY(fill_zero(st, gck, L.F));
-  PAT_TRY(fill_zero(st, SC, L.Sp));
-  PAT_TRY(fill_zero(st, SD, L.Sp));
+  PAT_TRY(fill_zero(st, a.uhx, L.F));
+  PAT_TRY(fill_zero(st, a.uhy, L.F));
+  PAT_TRY(fill_zero(st, a.rhx, L.F));
+  PAT_TRY(fill_zero(st, a.rhy, L.F));
+  PAT_TRY(fill_zero(st, a.gck, L.F));
+  PAT_TRY(fill_zero(st, a.SC, L.Sp));
+  PAT_TRY(fill_zero(st, a.SD, L.Sp));
+  PAT_TRY(set_ctl(st, a.ctl, 2 | 4, 0, g.nt, 0));
 
-  int seg0 = -1;   // checkpoint mode: the segment (n0, n0 + s] currently in the buffer
-  for (int n = g.nt - 1; n >= 1; --n) {
-    const float* p_n;
-    if (s == 0) {
-      p_n = hist + (size_t)n * fl;
-    } else {
-      const int n0 = ((n - 1) / s) * s;
-      if (n0 != seg0) {
-        // recompute p^{n0+1 .. n} from the checkpoint at n0 into the segment buffer
-        float *ux = at<float>(ws, L.ux), *uy = at<float>(ws, L.uy), *rx = at<float>(ws, L.rx),
-              *ry = at<float>(ws, L.ry);
-        float2 *SA = at<float2>(ws, L.SA), *SB = at<float2>(ws, L.SB);
-        if (n0 == 0) {
-          PAT_TRY(launch_fwd_init(p, st, c, p0, rx, ry, nullptr, nullptr, SA));
-        } else {
-          const int slot = n0 / s - 1;
-          const char* ck = at<char>(ws, L.ckpt) + (size_t)slot * (4 * align256(L.F) + align256(L.Sp));
-          PAT_TRY(copy_dev(st, ck, ux, L.F));
-          PAT_TRY(copy_dev(st, ck + align256(L.F), uy, L.F));
-          PAT_TRY(copy_dev(st, ck + 2 * align256(L.F), rx, L.F));
-          PAT_TRY(copy_dev(st, ck + 3 * align256(L.F), ry, L.F));
-          PAT_TRY(copy_dev(st, ck + 4 * align256(L.F), SA, L.Sp));
-        }
-        for (int j = n0; j < n; ++j)
-          PAT_TRY(forward_step(p, st, c, ux, uy, rx, ry, SA, SB, j, hist + (size_t)(j - n0) * fl, nullptr));
-        seg0 = n0;
-      }
-      p_n = hist + (size_t)(n - n0 - 1) * fl;
+  int n = g.nt - 1;   // next adjoint step
+  if (s == 0) {
+    while (n >= 1) {
+      const int cnt = std::min(kChunk, n);
+      PAT_TRY(run_steps(p, st, a, cnt, 2, abody));
+      n -= cnt;
     }
-    PAT_TRY(launch_col<COL_SUMM>(p, st, SC, SD, (float)(g.dt / g.rho0 * nrm)));
-    PAT_TRY(launch_adj_rho(p, st, c, p_n, resid + (size_t)n * p->m, rhx, rhy, gck, SC, SD));
-    PAT_TRY(launch_col<COL_PAIRP>(p, st, SC, SD, (float)(g.dt * g.rho0 * nrm)));
-    PAT_TRY(launch_adj_u(p, st, uhx, uhy, SC, SD, n == 1 ? 1 : 0));
+  } else {
+    FwdArgs f;
+    f.c = c;
+    f.ux = at<float>(ws, L.ux); f.uy = at<float>(ws, L.uy); f.rx = at<float>(ws, L.rx); f.ry = at<float>(ws, L.ry);
+    f.SA = at<float2>(ws, L.SA); f.SB = at<float2>(ws, L.SB);
+    f.hist_base = at<float>(ws, L.hist);   // the segment buffer: slot j holds level n0 + 1 + j
+    f.dpart = nullptr;
+    f.ctl = a.ctl;
+    while (n >= 1) {
+      const int n0 = ((n - 1) / s) * s;
+      // recompute p^{n0+1 .. n} from the checkpoint at n0 into the segment buffer
+      PAT_TRY(set_ctl(st, a.ctl, 1 | 4, n0 - 1, 0, n0 + 1));
+      if (n0 == 0) {
+        PAT_TRY(launch_fwd_init(p, st, c, p0, f.rx, f.ry, nullptr, nullptr, f.SA));
+      } else {
+        const int slot = n0 / s - 1;
+        const char* ck = at<char>(ws, L.ckpt) + (size_t)slot * (4 * align256(L.F) + align256(L.Sp));
+        PAT_TRY(copy_dev(st, ck, f.ux, L.F));
+        PAT_TRY(copy_dev(st, ck + align256(L.F), f.uy, L.F));
+        PAT_TRY(copy_dev(st, ck + 2 * align256(L.F), f.rx, L.F));
+        PAT_TRY(copy_dev(st, ck + 3 * align256(L.F), f.ry, L.F));
+        PAT_TRY(copy_dev(st, ck + 4 * align256(L.F), f.SA, L.Sp));
+      }
+      PAT_TRY(run_steps(p, st, f, n - n0, 3, fbody));
+      PAT_TRY(run_steps(p, st, a, n - n0, 2, abody));
+      n = n0;
+    }
   }
-  PAT_TRY(launch_col<COL_SUMM>(p, st, SC, SD, (float)(g.dt / g.rho0 * nrm)));
-  PAT_TRY(launch_adj_final(p, st, c, p0, resid, rhx, rhy, gck, g_p0, SC));
+  PAT_TRY(launch_col<COL_SUMM>(p, st, a.SC, a.SD, (float)(g.dt / g.rho0 * nrm), nullptr, 0));
+  PAT_TRY(launch_adj_final(p, st, c, p0, resid, a.rhx, a.rhy, a.gck, g_p0, a.SC));
   const int64_t npix = (int64_t)g.ny * g.nx;
-  hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, gck, g_c, p->K, npix);
+  hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, a.gck, g_c, p->K, npix);
   return last_error();
 }
 

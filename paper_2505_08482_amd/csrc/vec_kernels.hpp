@@ -39,6 +39,14 @@ __global__ void k_reduce_k(const float* __restrict__ gck, float* __restrict__ gc
   }
 }
 
+// Set fields of the step control block (mask bit 1: forward step, 2: adjoint
+// step, 4: first history slot).  One thread.
+__global__ void k_set_ctl(int32_t* __restrict__ ctl, int mask, int fwd_n, int adj_n, int hist_first) {
+  if (mask & 1) ctl[0] = fwd_n;
+  if (mask & 2) ctl[1] = adj_n;
+  if (mask & 4) ctl[2] = hist_first;
+}
+
 __global__ void k_fill_zero(float* __restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = 0.f;

@@ -39,6 +39,17 @@ struct ScatterTap {
   float w;
 };
 
+// Device control block (in the workspace): the step indices that the time-step
+// kernels read, so that a chunk of steps has identical launch arguments (and can
+// be replayed as one captured graph).  The first pass of each step advances the
+// counter; nothing else writes it.
+struct StepCtl {
+  int32_t fwd_n;       // forward update n -> n+1 in progress
+  int32_t adj_n;       // adjoint step n in progress
+  int32_t hist_first;  // time level stored in slot 0 of the pressure-history buffer
+  int32_t pad;
+};
+
 // Device tables owned by a plan.
 struct Tables {
   const float2* tw_x;   // [nx] exp(-2 pi i j / nx)
@@ -185,8 +196,10 @@ __global__ __launch_bounds__(256) void k_fwd_init(Tables tb, const float* __rest
 // Velocity update.  first != 0: u^{-1/2} = dt/(2 rho0) D+ p0 = G/2 (eq. (1): p_t(0) = 0).
 template <int NX>
 __global__ __launch_bounds__(256) void k_fwd_u(Tables tb, float* __restrict__ ux, float* __restrict__ uy,
-                                               float2* __restrict__ SA, float2* __restrict__ SB, int first) {
+                                               float2* __restrict__ SA, float2* __restrict__ SB,
+                                               const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
+  const int first = ctl->fwd_n == 0;
   __shared__ float2 Z[C::ROWS][C::PITCH];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
   const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
@@ -227,10 +240,13 @@ __global__ __launch_bounds__(256) void k_fwd_u(Tables tb, float* __restrict__ ux
 // Density / pressure update, sensors at time level n+1, history, row spectra of p.
 template <int NX>
 __global__ __launch_bounds__(256) void k_fwd_rho(Tables tb, const float* __restrict__ c, float* __restrict__ rx,
-                                                 float* __restrict__ ry, float* __restrict__ hist,
-                                                 float* __restrict__ dpart_n, float2* __restrict__ SA,
-                                                 const float2* __restrict__ SB) {
+                                                 float* __restrict__ ry, float* __restrict__ hist_base,
+                                                 float* __restrict__ dpart, float2* __restrict__ SA,
+                                                 const float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
+  const int n = ctl->fwd_n;
+  float* hist = hist_base ? hist_base + (size_t)(n + 1 - ctl->hist_first) * tb.K * tb.ny * NX : nullptr;
+  float* dpart_n = dpart ? dpart + (size_t)(n + 1) * 2 * tb.m : nullptr;
   __shared__ float2 Z[C::ROWS][C::PITCH];
   __shared__ float P[C::ROWS][NX];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
@@ -289,8 +305,10 @@ enum ColMode : int {
 
 template <int NY, int MODE>
 __global__ __launch_bounds__(ColCfg<NY>::BLOCK) void k_col(Tables tb, float2* __restrict__ SA,
-                                                           float2* __restrict__ SB, float scale) {
+                                                           float2* __restrict__ SB, float scale,
+                                                           int32_t* __restrict__ step, int32_t delta) {
   using C = ColCfg<NY>;
+  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;   // first pass of a step
   __shared__ float2 A[C::TC][C::PITCH];
   __shared__ float2 B[C::TC][C::PITCH];
   const int K = tb.K, nh = tb.nh;
@@ -357,11 +375,14 @@ __global__ __launch_bounds__(ColCfg<NY>::BLOCK) void k_col(Tables tb, float2* __
 // gc += (2/c) p^n ph; spectra of (a_x rh_x, a_y rh_y); then rh <- a^2 rh.
 template <int NX>
 __global__ __launch_bounds__(256) void k_adj_rho(Tables tb, const float* __restrict__ c,
-                                                 const float* __restrict__ p_n, const float* __restrict__ resid_n,
+                                                 const float* __restrict__ hist_base, const float* __restrict__ resid,
                                                  float* __restrict__ rhx, float* __restrict__ rhy,
                                                  float* __restrict__ gck, float2* __restrict__ SA,
-                                                 float2* __restrict__ SB) {
+                                                 float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
+  const int n = ctl->adj_n;
+  const float* p_n = hist_base + (size_t)(n - ctl->hist_first) * tb.K * tb.ny * NX;
+  const float* resid_n = resid + (size_t)n * tb.m;
   __shared__ float2 Z[C::ROWS][C::PITCH];
   __shared__ float PH[C::ROWS][NX];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
@@ -427,11 +448,13 @@ __global__ __launch_bounds__(256) void k_adj_rho(Tables tb, const float* __restr
 }
 
 // uh <- as^2 uh + (inverse rows of the PAIRP spectra); spectra of (w_x uh_x, w_y uh_y)
-// with w = as (next step) or as - as^2/2 (closing term, final = 1).
+// with w = as (next step) or as - as^2/2 (closing term, at adjoint step n = 1).
 template <int NX>
 __global__ __launch_bounds__(256) void k_adj_u(Tables tb, float* __restrict__ uhx, float* __restrict__ uhy,
-                                               float2* __restrict__ SA, float2* __restrict__ SB, int final_) {
+                                               float2* __restrict__ SA, float2* __restrict__ SB,
+                                               const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
+  const int final_ = ctl->adj_n == 1;
   __shared__ float2 Z[C::ROWS][C::PITCH];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
   const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
