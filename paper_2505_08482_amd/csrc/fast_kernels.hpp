@@ -28,23 +28,27 @@ namespace pat {
 namespace fast {
 
 template <int N> struct Cfg;
-template <> struct Cfg<512> { static constexpr int T = 64; using L = RList<8, 8, 8>; static constexpr int TC = 8; };
-template <> struct Cfg<256> { static constexpr int T = 32; using L = RList<8, 8, 4>; static constexpr int TC = 8; };
-template <> struct Cfg<128> { static constexpr int T = 16; using L = RList<8, 4, 4>; static constexpr int TC = 16; };
-template <> struct Cfg<64>  { static constexpr int T = 8;  using L = RList<8, 8>;    static constexpr int TC = 32; };
-template <> struct Cfg<32>  { static constexpr int T = 4;  using L = RList<8, 4>;    static constexpr int TC = 64; };
+// T threads per transform (8 elements each); TC adjacent columns per column
+// block (at least one wave, at least 4 columns = 32-byte row segments; narrow
+// tiles give several blocks per CU).
+template <> struct Cfg<512> { static constexpr int T = 64; using L = RList<8, 8, 8>; static constexpr int TC = 4; };
+template <> struct Cfg<256> { static constexpr int T = 32; using L = RList<8, 8, 4>; static constexpr int TC = 4; };
+template <> struct Cfg<128> { static constexpr int T = 16; using L = RList<8, 4, 4>; static constexpr int TC = 4; };
+template <> struct Cfg<64>  { static constexpr int T = 8;  using L = RList<8, 8>;    static constexpr int TC = 8; };
+template <> struct Cfg<32>  { static constexpr int T = 4;  using L = RList<8, 4>;    static constexpr int TC = 16; };
 
 // LDS position of element i: one pad slot per 8 keeps the radix-8 exchanges
 // (stride-8 writes, stride-1 reads) free of bank conflicts within a transform.
 __device__ __forceinline__ int phys(int i) { return i + (i >> 3); }
 // Pitch of one transform.  Row passes: one transform per lane group.  Column
-// passes interleave TC columns across the lanes of a wave: a pitch of 2 (mod 16)
-// complex spreads 8 columns x 2 rows of a 16-lane group over all 32 banks, an
-// odd pitch spreads 16 columns.
+// passes interleave TC columns across the lanes of a wave; a 16-lane group then
+// holds TC columns x 16/TC rows, spread over all 32 banks by a pitch of
+// 4 (mod 16) complex for TC = 4, 2 (mod 16) for TC = 8, odd for TC = 16.
 template <int N> struct Lds { static constexpr int P = N + N / 8 + 2; };
 template <int N> struct LdsCol {
   static constexpr int base = N + N / 8;
-  static constexpr int P = Cfg<N>::TC == 8 ? base + ((18 - base % 16) % 16) : (base | 1);
+  static constexpr int want = Cfg<N>::TC == 4 ? 4 : (Cfg<N>::TC == 8 ? 2 : 1);
+  static constexpr int P = Cfg<N>::TC >= 16 ? (base | 1) : base + ((16 + want - base % 16) % 16);
 };
 
 // One register-resident Stockham stage on NV transforms at once (shared barriers).
@@ -144,18 +148,33 @@ template <int N> using Fft = RegFft<N, typename Cfg<N>::L>;
 // ---------------------------------------------------------------------------
 // Folded half spectra along a row of length N (h = N/2 entries)
 // ---------------------------------------------------------------------------
-// z[k] = a[k] + i b[k] for the two real rows whose folded spectra are A, B.
-__device__ __forceinline__ float2 pack_folded(const float2* __restrict__ A, const float2* __restrict__ B, int k,
-                                              int N) {
-  const int h = N >> 1;
-  if (k == 0) return make_float2(A[0].x, B[0].x);
-  if (k == h) return make_float2(A[0].y, B[0].y);
-  if (k < h) {
+// z[k] = a[k] + i b[k] for the two real rows whose folded spectra are A, B, at
+// the owned bin k = q + T*M (N = 8T).  Bins M < 4 are stored directly; bins
+// M >= 4 are mirrored (k > N/2, conjugate of bin N - k); the only special bins
+// (k = 0 and k = N/2, both in lane q = 0) are chosen by select, not by branch.
+template <int N, int M>
+__device__ __forceinline__ float2 pack_folded(const float2* __restrict__ A, const float2* __restrict__ B, int q) {
+  constexpr int T = N / 8;
+  const int k = q + T * M;
+  if constexpr (M < 4) {
     const float2 a = A[k], b = B[k];
-    return make_float2(a.x - b.y, a.y + b.x);
+    const float2 gen = make_float2(a.x - b.y, a.y + b.x);
+    if constexpr (M == 0) return q == 0 ? make_float2(a.x, b.x) : gen;   // DC: real parts
+    return gen;
+  } else {
+    const int idx = (M == 4 && q == 0) ? 0 : N - k;
+    const float2 a = A[idx], b = B[idx];
+    const float2 gen = make_float2(a.x + b.y, b.x - a.y);                 // conj(a) + i conj(b)
+    if constexpr (M == 4) return q == 0 ? make_float2(a.y, b.y) : gen;   // Nyquist, folded into bin 0
+    return gen;
   }
-  const float2 a = A[N - k], b = B[N - k];
-  return make_float2(a.x + b.y, b.x - a.y);
+}
+
+template <int N, int M = 0>
+__device__ __forceinline__ void pack_row(float2 (&v)[8], const float2* __restrict__ A, const float2* __restrict__ B,
+                                         int q) {
+  v[M] = pack_folded<N, M>(A, B, q);
+  if constexpr (M + 1 < 8) pack_row<N, M + 1>(v, A, B, q);
 }
 
 // Split the transform of a + i b (held in owner layout, element q + T m in v[m])
@@ -164,29 +183,25 @@ template <int N>
 __device__ __forceinline__ void unpack_store(const float2 (&v)[8], int q, int lane_base, float2* __restrict__ rowA,
                                              float2* __restrict__ rowB) {
   constexpr int T = Cfg<N>::T;
-  float2 part[4];
+  const int src = lane_base + ((T - q) & (T - 1));
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const int src = lane_base + ((T - q) & (T - 1));
+    // partner bin N - k: lane T - q, register 7 - m (lane 0: its own register 8 - m)
     const float px = __shfl(v[7 - m].x, src);
     const float py = __shfl(v[7 - m].y, src);
-    part[m] = q == 0 ? v[(8 - m) & 7] : make_float2(px, py);
-  }
-  // owned k = q + T m <= N/2 : m < 4, or m == 4 for q == 0 (the Nyquist bin)
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
+    const float2 part = q == 0 ? v[(8 - m) & 7] : make_float2(px, py);
     const int k = q + T * m;
-    const float2 P = v[m], Q = make_float2(part[m].x, -part[m].y);   // Z[k], conj Z[N-k]
-    const float2 A = make_float2(0.5f * (P.x + Q.x), 0.5f * (P.y + Q.y));
-    const float2 B = make_float2(0.5f * (P.y - Q.y), -0.5f * (P.x - Q.x));
-    if (k == 0) {
-      const float2 Zn = v[4];   // k = N/2 belongs to q = 0, m = 4: A = Re, B = Im
-      rowA[0] = make_float2(P.x, Zn.x);
-      rowB[0] = make_float2(P.y, Zn.y);
-    } else {
-      rowA[k] = A;
-      rowB[k] = B;
+    const float2 P = v[m], Q = make_float2(part.x, -part.y);   // Z[k], conj Z[N-k]
+    float2 A = make_float2(0.5f * (P.x + Q.x), 0.5f * (P.y + Q.y));
+    float2 B = make_float2(0.5f * (P.y - Q.y), -0.5f * (P.x - Q.x));
+    if (m == 0) {
+      // k = 0 (lane 0): DC parts, with the Nyquist bin (q = 0, m = 4) folded in
+      const float2 Zn = v[4];
+      A = q == 0 ? make_float2(P.x, Zn.x) : A;
+      B = q == 0 ? make_float2(P.y, Zn.y) : B;
     }
+    rowA[k] = A;
+    rowB[k] = B;
   }
 }
 
@@ -268,27 +283,33 @@ __global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux,
     const float2* A = SA + ((size_t)k * ny + y) * nhf;
     const float2* B = SB + ((size_t)k * ny + y) * nhf;
     const size_t f = ((size_t)k * ny + y) * N;
+    pack_row<N>(v[h], A, B, q);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      v[h][m] = pack_folded(A, B, q + T * m, N);
       if (!first) {
         ox[h][m] = ux[f + q + T * m];
         oy[h][m] = uy[f + q + T * m];
       }
     }
   }
+  // PML factors (prefetched before the transforms)
+  float pax[8], pay[2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) pax[m] = tb.asx[q + T * m];
+  pay[0] = tb.asy[ok ? y0 : 0];
+  pay[1] = tb.asy[ok ? y1 : 0];
   float2* L[2] = {X[grp][0], X[grp][1]};
   fft.template run<+1, 2>(v, L, q);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
-    const float ays = tb.asy[y];
+    const float ays = pay[h];
     const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int x = q + T * m;
       const float2 g = v[h][m];
-      const float axs = tb.asx[x];
+      const float axs = pax[m];
       const float uxo = first ? 0.5f * g.x : ox[h][m];
       const float uyo = first ? 0.5f * g.y : oy[h][m];
       const float nux = axs * (axs * uxo - g.x);
@@ -331,15 +352,20 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
     const float2* A = SA + ((size_t)k * ny + y) * nhf;
     const float2* B = SB + ((size_t)k * ny + y) * nhf;
     const size_t f = ((size_t)k * ny + y) * N;
+    pack_row<N>(v[h], A, B, q);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int x = q + T * m;
-      v[h][m] = pack_folded(A, B, x, N);
       orx[h][m] = rx[f + x];
       ory[h][m] = ry[f + x];
       cc[h][m] = c[(size_t)y * N + x];
     }
   }
+  float pax[8], pay[2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) pax[m] = tb.ax[q + T * m];
+  pay[0] = tb.ay[ok ? y0 : 0];
+  pay[1] = tb.ay[ok ? y1 : 0];
   // sensor taps of this block's rows (one entry per thread, prefetched)
   const int g0 = tb.g_row_start[ybase], g1 = tb.g_row_start[min(ybase + RC::ROWS, ny)];
   GatherEnt ge{};
@@ -351,13 +377,13 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
-    const float ays = tb.ay[y];
+    const float ays = pay[h];
     const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int x = q + T * m;
       const float2 d = v[h][m];
-      const float axs = tb.ax[x];
+      const float axs = pax[m];
       const float nrx = axs * (axs * orx[h][m] - d.x);
       const float nry = ays * (ays * ory[h][m] - d.y);
       const float p = (cc[h][m] * cc[h][m]) * (nrx + nry);
@@ -414,8 +440,7 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
   {
     const float2* A = SA + ((size_t)k * ny + (ok ? y0 : 0)) * nhf;
     const float2* B = SA + ((size_t)k * ny + (ok ? y1 : 0)) * nhf;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) v[0][m] = pack_folded(A, B, q + T * m, N);
+    pack_row<N>(v[0], A, B, q);
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -431,6 +456,17 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
       oc[h][m] = c[(size_t)y * N + x];
     }
   }
+  float pax[8], pax2[8], pay[2], pay2[2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    pax[m] = tb.ax[q + T * m];
+    pax2[m] = tb.ax2[q + T * m];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    pay[h] = tb.ay[ok ? y0 + h : 0];
+    pay2[h] = tb.ay2[ok ? y0 + h : 0];
+  }
   // sensor injections of this block's rows: one pixel per thread (prefetched)
   const float* rk = resid_n + (size_t)k * tb.nt * tb.m;
   const int e0 = tb.s_row_start[ybase], e1 = tb.s_row_start[min(ybase + RC::ROWS, ny)];
@@ -439,7 +475,10 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
   int inj_at = -1;
   if (e < e1) {
     const ScatterPix px = tb.s_pix[e];
-    for (int t = 0; t < px.count; ++t) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < px.count) inj += px.w[t] * rk[px.sensor[t]];
+    for (int t = 4; t < px.count; ++t) {
       const ScatterTap tp = tb.s_tap[px.start + t];
       inj += tp.w * rk[tp.sensor];
     }
@@ -470,7 +509,7 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
-    const float ays = tb.ay[y], ay2s = tb.ay2[y];
+    const float ays = pay[h], ay2s = pay2[h];
     const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -480,13 +519,14 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
       const float c2 = cv * cv;
       const float nrx = orx[h][m] + c2 * ph;
       const float nry = ory[h][m] + c2 * ph;
-      const float gnew = og[h][m] + (2.0f / cv) * op[h][m] * ph;
+      // 2/c with the hardware reciprocal (1 ulp): the sound-speed sensitivity term
+      const float gnew = og[h][m] + (2.0f * __builtin_amdgcn_rcpf(cv)) * op[h][m] * ph;
       if (ok) {
         gck[f + x] = gnew;
-        rhx[f + x] = tb.ax2[x] * nrx;
+        rhx[f + x] = pax2[m] * nrx;
         rhy[f + x] = ay2s * nry;
       }
-      w[h][m] = make_float2(tb.ax[x] * nrx, ays * nry);
+      w[h][m] = make_float2(pax[m] * nrx, ays * nry);
     }
   }
   float2* L[2] = {X[grp][0], X[grp][1]};
@@ -518,33 +558,45 @@ __global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx
     const float2* A = SA + ((size_t)k * ny + y) * nhf;
     const float2* B = SB + ((size_t)k * ny + y) * nhf;
     const size_t f = ((size_t)k * ny + y) * N;
+    pack_row<N>(v[h], A, B, q);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      v[h][m] = pack_folded(A, B, q + T * m, N);
       ox[h][m] = uhx[f + q + T * m];
       oy[h][m] = uhy[f + q + T * m];
     }
   }
+  const float* wxt = final_ ? tb.wfx : tb.asx;
+  const float* wyt = final_ ? tb.wfy : tb.asy;
+  float pa2x[8], pwx[8], pa2y[2], pwy[2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    pa2x[m] = tb.asx2[q + T * m];
+    pwx[m] = wxt[q + T * m];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    pa2y[h] = tb.asy2[ok ? y0 + h : 0];
+    pwy[h] = wyt[ok ? y0 + h : 0];
+  }
   float2* L[2] = {X[grp][0], X[grp][1]};
   fft.template run<+1, 2>(v, L, q);
-  const float* wxt = final_ ? tb.wfx : tb.asx;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
-    const float a2y = tb.asy2[y];
-    const float wy = final_ ? tb.wfy[y] : tb.asy[y];
+    const float a2y = pa2y[h];
+    const float wy = pwy[h];
     const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int x = q + T * m;
       const float2 g = v[h][m];
-      const float nux = tb.asx2[x] * ox[h][m] + g.x;
+      const float nux = pa2x[m] * ox[h][m] + g.x;
       const float nuy = a2y * oy[h][m] + g.y;
       if (ok) {
         uhx[f + x] = nux;
         uhy[f + x] = nuy;
       }
-      v[h][m] = make_float2(wxt[x] * nux, wy * nuy);
+      v[h][m] = make_float2(pwx[m] * nux, wy * nuy);
     }
   }
   fft.template run<-1, 2>(v, L, q);
@@ -571,8 +623,7 @@ __global__ __launch_bounds__(64) void k_adj_final(Tables tb, const float* __rest
   {
     const float2* A = SA + ((size_t)k * ny + (ok ? y0 : 0)) * nhf;
     const float2* B = SA + ((size_t)k * ny + (ok ? y1 : 0)) * nhf;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) v[0][m] = pack_folded(A, B, q + T * m, N);
+    pack_row<N>(v[0], A, B, q);
   }
   float2* L1[1] = {X[grp]};
   fft.template run<+1, 1>(v, L1, q);
@@ -610,7 +661,8 @@ __global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float
                                                                 int32_t* __restrict__ step, int32_t delta) {
   if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;   // first pass of a step
   constexpr int T = Cfg<N>::T, TC = Cfg<N>::TC, P = LdsCol<N>::P;
-  static_assert(TC != 8 || P % 16 == 2, "column pitch");
+  static_assert((TC == 4 && P % 16 == 4) || (TC == 8 && P % 16 == 2) || (TC >= 16 && P % 2 == 1),
+                "column pitch");
   constexpr bool TWO_IN = MODE != COL_GRAD1;
   constexpr bool TWO_OUT = MODE != COL_SUMM;
   __shared__ float2 LA[TC * P];
@@ -629,6 +681,22 @@ __global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float
     a[0][m] = SA[i];
     if (TWO_IN) a[1][m] = SB[i];
   }
+  // spectral multiplier factors (prefetched before the transforms)
+  constexpr bool PLUS = MODE == COL_GRAD1 || MODE == COL_PAIRP;
+  const float2* eyt = PLUS ? tb.ey_p : tb.ey_m;
+  const float2* ext = PLUS ? tb.ex_p : tb.ex_m;
+  const bool col0 = c0 == 0 && cl == 0;   // DC + i Nyquist column
+  float kap[8], kapN[8];
+  float2 eyv[8];
+  const float2 exv = ext[col0 ? 0 : (ok ? cx : 0)];
+  const float2 exN = ext[nx / 2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int e = q + T * m;
+    kap[m] = tb.kappa[(size_t)e * nh + (ok ? cx : 0)] * scale;
+    kapN[m] = col0 ? tb.kappa[(size_t)e * nh + nx / 2] * scale : 0.f;
+    eyv[m] = eyt[e];
+  }
   float2* LL[2] = {LA + cl * P, LB + cl * P};
   if (TWO_IN)
     fft.template run<-1, 2>(a, LL, q);
@@ -646,13 +714,11 @@ __global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float
     }
     __syncthreads();
     if (cl == 0) {
-      const float2 e0p = tb.ex_p[0], e0m = tb.ex_m[0], eNp = tb.ex_p[nx / 2], eNm = tb.ex_m[nx / 2];
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int e = q + T * m, ep = (N - e) & (N - 1);
-        const float k0 = tb.kappa[(size_t)e * nh] * scale;
-        const float kN = tb.kappa[(size_t)e * nh + nx / 2] * scale;
-        const float2 eyp = tb.ey_p[e], eym = tb.ey_m[e];
+        const float k0 = kap[m], kN = kapN[m];
+        const float2 ey = eyv[m];
         float2 ZA = a[0][m], ZAp = LA[phys(ep)];
         // A0 = (Z + conj Zp)/2 (DC column), AN = (Z - conj Zp)/(2i) (Nyquist column)
         float2 A0 = make_float2(0.5f * (ZA.x + ZAp.x), 0.5f * (ZA.y - ZAp.y));
@@ -665,17 +731,14 @@ __global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float
         }
         float2 o0, oN, p0_, pN;
         if (MODE == COL_GRAD1) {
-          o0 = cscale(cmul(A0, e0p), k0); oN = cscale(cmul(AN, eNp), kN);
-          p0_ = cscale(cmul(A0, eyp), k0); pN = cscale(cmul(AN, eyp), kN);
-        } else if (MODE == COL_PAIRP) {
-          o0 = cscale(cmul(A0, e0p), k0); oN = cscale(cmul(AN, eNp), kN);
-          p0_ = cscale(cmul(B0, eyp), k0); pN = cscale(cmul(BN, eyp), kN);
-        } else if (MODE == COL_PAIRM) {
-          o0 = cscale(cmul(A0, e0m), k0); oN = cscale(cmul(AN, eNm), kN);
-          p0_ = cscale(cmul(B0, eym), k0); pN = cscale(cmul(BN, eym), kN);
+          o0 = cscale(cmul(A0, exv), k0); oN = cscale(cmul(AN, exN), kN);
+          p0_ = cscale(cmul(A0, ey), k0); pN = cscale(cmul(AN, ey), kN);
+        } else if (MODE == COL_PAIRP || MODE == COL_PAIRM) {
+          o0 = cscale(cmul(A0, exv), k0); oN = cscale(cmul(AN, exN), kN);
+          p0_ = cscale(cmul(B0, ey), k0); pN = cscale(cmul(BN, ey), kN);
         } else {
-          o0 = cscale(cadd(cmul(A0, e0m), cmul(B0, eym)), k0);
-          oN = cscale(cadd(cmul(AN, eNm), cmul(BN, eym)), kN);
+          o0 = cscale(cadd(cmul(A0, exv), cmul(B0, ey)), k0);
+          oN = cscale(cadd(cmul(AN, exN), cmul(BN, ey)), kN);
           p0_ = o0; pN = oN;
         }
         // recombine: out = o0 + i oN
@@ -684,24 +747,18 @@ __global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float
       }
     }
   }
-  if (!(c0 == 0 && cl == 0)) {
-    const float2 exp_ = tb.ex_p[ok ? cx : 0], exm = tb.ex_m[ok ? cx : 0];
+  if (!col0) {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int e = q + T * m;
-      const float kap = tb.kappa[(size_t)e * nh + (ok ? cx : 0)] * scale;
       const float2 x0 = a[0][m];
       if (MODE == COL_GRAD1) {
-        a[0][m] = cscale(cmul(x0, exp_), kap);
-        a[1][m] = cscale(cmul(x0, tb.ey_p[e]), kap);
-      } else if (MODE == COL_PAIRP) {
-        a[0][m] = cscale(cmul(x0, exp_), kap);
-        a[1][m] = cscale(cmul(a[1][m], tb.ey_p[e]), kap);
-      } else if (MODE == COL_PAIRM) {
-        a[0][m] = cscale(cmul(x0, exm), kap);
-        a[1][m] = cscale(cmul(a[1][m], tb.ey_m[e]), kap);
+        a[0][m] = cscale(cmul(x0, exv), kap[m]);
+        a[1][m] = cscale(cmul(x0, eyv[m]), kap[m]);
+      } else if (MODE == COL_PAIRP || MODE == COL_PAIRM) {
+        a[0][m] = cscale(cmul(x0, exv), kap[m]);
+        a[1][m] = cscale(cmul(a[1][m], eyv[m]), kap[m]);
       } else {
-        a[0][m] = cscale(cadd(cmul(x0, exm), cmul(a[1][m], tb.ey_m[e])), kap);
+        a[0][m] = cscale(cadd(cmul(x0, exv), cmul(a[1][m], eyv[m])), kap[m]);
       }
     }
   }

@@ -586,8 +586,15 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   std::vector<ScatterTap> stap;
   for (size_t i = 0; i < taps.size();) {
     size_t j = i;
-    ScatterPix px{taps[i].row, taps[i].ix, (int32_t)stap.size(), 0};
+    ScatterPix px{};
+    px.row = taps[i].row;
+    px.ix = taps[i].ix;
+    px.start = (int32_t)stap.size();
     while (j < taps.size() && taps[j].row == taps[i].row && taps[j].ix == taps[i].ix) {
+      if (j - i < 4) {
+        px.sensor[j - i] = taps[j].sensor;
+        px.w[j - i] = taps[j].w;
+      }
       stap.push_back({taps[j].sensor, taps[j].w});
       ++j;
     }

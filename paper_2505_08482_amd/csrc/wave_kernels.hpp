@@ -32,7 +32,9 @@ struct GatherEnt {   // one (sensor, tap row) pair: partial = w0 p[ix0] + w1 p[i
   float w0, w1;
 };
 struct ScatterPix {  // one pixel receiving sensor injections: sum over its taps
-  int32_t row, ix, start, count;
+  int32_t row, ix, start, count;   // taps s_tap[start .. start + count)
+  int32_t sensor[4];               // the first four taps inline (one load for the usual case)
+  float w[4];
 };
 struct ScatterTap {
   int32_t sensor;
