@@ -1,0 +1,230 @@
+"""Joint reconstruction of the K initial pressures and the shared sound speed
+(Sec. 3, Sec. 3.1) on top of the C ABI.
+
+* objective and gradient: ``pat_forward`` (recorded) + ``pat_misfit`` +
+  ``pat_adjoint_gradient`` (eq. (4) data term, eqs. (5)-(9));
+* step: eq. (10) ``x <- P(x - alpha H g)`` with ``pat_lbfgs_direction``
+  (Alg. 1, memory l) and ``pat_project_update`` (eq. (11)), backtracking
+  (Armijo) line search with trial forward solves only;
+* multigrid continuation (Sec. 3.1): coarse-to-fine levels, the converged
+  iterate carried to the next level with ``pat_prolong`` and the data
+  resampled onto each level's time grid with ``pat_time_interp`` (Sec. 4.1.2).
+
+The optimiser works on scaled variables ``z = x / scale`` (per block: p0 and c).
+Its decisions (active set, direction safeguards, Armijo test, pair filter) are
+the ones of the float64 reference driver; the few elementwise vector updates
+between library calls (scaling, pair differences) are plain torch arithmetic.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import pat
+
+
+@dataclasses.dataclass
+class LevelResult:
+    n: int
+    iters: int
+    evals: int
+    J: List[float]
+    seconds: float
+    E_c: List[float]
+
+
+class Problem:
+    """One grid level: K datasets, observed traces y, weights w, bounds."""
+
+    def __init__(self, wl: I.Workload, y: torch.Tensor, w: torch.Tensor, c_lo: float, c_hi: float,
+                 c_fixed: float = 1500.0, ckpt_every: int = 0, device="cuda"):
+        self.wl = wl
+        g = wl.grid
+        self.plan = pat.Plan(g, wl.K, wl.sensors)
+        self.ws = self.plan.workspace(ckpt_every, device=device)
+        self.ckpt = ckpt_every
+        self.y = y.contiguous()
+        self.w = w.contiguous()
+        self.N = g.nx * g.ny
+        self.K = wl.K
+        self.n = (self.K + 1) * self.N
+        mask = torch.from_numpy(I.mask_disc(g.nx, wl.support_radius_px).astype(np.bool_)).to(device)
+        # bounds (eq. (11)): p0 >= 0, c in [c_lo, c_hi]; outside the mask both are pinned
+        lo = torch.empty(self.n, dtype=torch.float32, device=device)
+        hi = torch.empty_like(lo)
+        lo[: self.K * self.N] = 0.0
+        hi[: self.K * self.N] = float("inf")
+        lo[self.K * self.N:] = c_lo
+        hi[self.K * self.N:] = c_hi
+        outside = ~mask.reshape(-1)
+        for k in range(self.K + 1):
+            sl = slice(k * self.N, (k + 1) * self.N)
+            fixed = c_fixed if k == self.K else 0.0
+            lo[sl][outside] = fixed
+            hi[sl][outside] = fixed
+        self.scale = torch.empty_like(lo)
+        self.scale[: self.K * self.N] = 0.25
+        self.scale[self.K * self.N:] = (c_hi - c_lo) / 4.0
+        self.lo_z = lo / self.scale
+        self.hi_z = hi / self.scale
+        self.mask = mask
+        self.data = torch.empty(self.plan.data_shape, dtype=torch.float32, device=device)
+        self.resid = torch.empty_like(self.data)
+        self.J = torch.zeros(1, dtype=torch.float64, device=device)
+        self.gp0 = torch.empty(self.plan.field_shape, dtype=torch.float32, device=device)
+        self.gc = torch.empty((g.ny, g.nx), dtype=torch.float32, device=device)
+        self.dot_scratch = torch.empty(pat.lbfgs_scratch_bytes(0), dtype=torch.uint8, device=device)
+        self.dot_out = torch.zeros(1, dtype=torch.float64, device=device)
+        self.evals = 0
+
+    def split(self, x: torch.Tensor):
+        """Physical (p0 [K][ny][nx], c [ny][nx]) views of a physical stacked vector."""
+        g = self.wl.grid
+        return x[: self.K * self.N].view(self.K, g.ny, g.nx), x[self.K * self.N:].view(g.ny, g.nx)
+
+    def objective(self, z: torch.Tensor) -> float:
+        """J at scaled point z (recorded forward solve + misfit)."""
+        self.x = z * self.scale            # kept alive: the adjoint reuses these buffers
+        p0, c = self.split(self.x)
+        self.plan.forward(c, p0, self.data, self.ws, ckpt_every=self.ckpt, record=True)
+        self.plan.misfit(self.data, self.y, self.w, self.resid, self.J)
+        self.evals += 1
+        return float(self.J.item())
+
+    def gradient(self) -> torch.Tensor:
+        """Scaled gradient at the point of the last ``objective`` call."""
+        p0, c = self.split(self.x)
+        self.plan.adjoint_gradient(c, p0, self.resid, self.gp0, self.gc, self.ws)
+        return torch.cat([self.gp0.reshape(-1), self.gc.reshape(-1)]) * self.scale
+
+    def dot(self, a, b) -> float:
+        pat.dot(a, b, self.dot_out, self.dot_scratch)
+        return float(self.dot_out.item())
+
+    def close(self):
+        self.plan.close()
+
+
+def projected_lbfgs(prob: Problem, z0: torch.Tensor, iters: int, memory: int = 20, c1: float = 1e-4,
+                    max_halvings: int = 20, callback: Optional[Callable] = None):
+    """Eq. (10) iterations on scaled variables (see the module docstring)."""
+    z = z0.clone()
+    pat.project_update(z, torch.zeros_like(z), 0.0, prob.lo_z, prob.hi_z)
+    J = prob.objective(z)
+    g = prob.gradient()
+    S: List[torch.Tensor] = []
+    Y: List[torch.Tensor] = []
+    scratch = torch.empty(pat.lbfgs_scratch_bytes(memory), dtype=torch.uint8, device=z.device)
+    hist = [J]
+    d = torch.empty_like(z)
+    it = 0
+    for it in range(iters):
+        active = ((z <= prob.lo_z) & (g > 0)) | ((z >= prob.hi_z) & (g < 0))
+        gf = torch.where(active, torch.zeros_like(g), g)
+        use_qn = bool(S)
+        if use_qn:
+            pat.lbfgs_direction(gf, S, Y, d, scratch)
+            d = torch.where(active, torch.zeros_like(d), d)
+            if prob.dot(d, gf) <= 0.0:
+                S.clear(); Y.clear()
+                use_qn = False
+        if not use_qn:
+            nrm = float(gf.abs().max().item())
+            if nrm == 0.0:
+                break
+            d = gf / nrm
+        accepted = False
+        zt = torch.empty_like(z)
+        for attempt in range(2):
+            alpha = 1.0
+            for _ in range(max_halvings):
+                zt.copy_(z)
+                pat.project_update(zt, d, alpha, prob.lo_z, prob.hi_z)
+                Jt = prob.objective(zt)
+                if np.isfinite(Jt) and Jt <= J + c1 * prob.dot(g, zt - z):
+                    accepted = True
+                    break
+                alpha *= 0.5
+            if accepted or not use_qn:
+                break
+            S.clear(); Y.clear()
+            use_qn = False
+            d = gf / float(gf.abs().max().item())
+        if not accepted:
+            break
+        gt = prob.gradient()    # adjoint of the accepted trial's recorded forward solve
+        s_ = zt - z
+        y_ = gt - g
+        ys = prob.dot(y_, s_)
+        if ys > 1e-10 * float(torch.linalg.vector_norm(y_).item()) * float(torch.linalg.vector_norm(s_).item()):
+            S.append(s_); Y.append(y_)
+            if len(S) > memory:
+                S.pop(0); Y.pop(0)
+        z, J, g = zt, Jt, gt
+        hist.append(J)
+        if callback is not None:
+            callback(it, z, J)
+    return z, J, hist, it + 1
+
+
+def relative_error_c(prob: Problem, z: torch.Tensor, c_true: torch.Tensor) -> float:
+    """Eq. (12) for c over the reconstruction mask, in percent."""
+    _, c = prob.split(z * prob.scale)
+    m = prob.mask
+    return 100.0 * float(torch.linalg.vector_norm((c - c_true)[m]) / torch.linalg.vector_norm(c_true[m]))
+
+
+def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w: torch.Tensor, c_true_fine,
+              c_lo: float = 1400.0, c_hi: float = 1600.0, iters: int = 40, memory: int = 20,
+              ckpt_every: int = 0, target_Ec: Optional[float] = None, log: Optional[Callable] = None):
+    """Coarse-to-fine reconstruction (Sec. 3.1).  ``c_true_fine`` (torch, finest
+    grid) only measures E_c; it never enters the optimisation."""
+    device = y_fine.device
+    results: List[LevelResult] = []
+    z_prev = None
+    prev = None
+    t_all = time.perf_counter()
+    for li, wl in enumerate(levels):
+        g = wl.grid
+        y = torch.empty((wl.K, g.nt, wl.m), dtype=torch.float32, device=device)
+        pat.time_interp(y_fine, dt_fine, y, g.dt)
+        prob = Problem(wl, y, w, c_lo, c_hi, ckpt_every=ckpt_every)
+        if z_prev is None:
+            x0 = torch.empty(prob.n, dtype=torch.float32, device=device)
+            x0[: prob.K * prob.N] = 0.0
+            x0[prob.K * prob.N:] = 0.5 * (c_lo + c_hi)
+        else:
+            xc = (z_prev * prev.scale).view(prev.K + 1, prev.wl.grid.ny, prev.wl.grid.nx).contiguous()
+            xf = torch.empty((prob.K + 1, g.ny, g.nx), dtype=torch.float32, device=device)
+            pat.prolong(xc, xf)
+            x0 = xf.reshape(-1)
+            prev.close()
+        z0 = x0 / prob.scale
+        ct = c_true_fine
+        if ct.shape[-1] != g.nx:
+            ctf = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=device)
+            pat.prolong(c_true_fine.reshape(1, *c_true_fine.shape).contiguous(), ctf)
+            ct = ctf[0]
+        Ec = []
+        t0 = time.perf_counter()
+
+        def cb(it, z, J):
+            Ec.append(relative_error_c(prob, z, ct))
+            if log:
+                log(f"level {g.nx}: iter {it + 1} J {J:.6e} E_c {Ec[-1]:.3f} %")
+
+        z, J, hist, nit = projected_lbfgs(prob, z0, iters, memory=memory, callback=cb)
+        torch.cuda.synchronize()
+        results.append(LevelResult(g.nx, nit, prob.evals, hist, time.perf_counter() - t0, Ec))
+        z_prev, prev = z, prob
+    x = z_prev * prev.scale
+    p0, c = prev.split(x)
+    out = {"levels": results, "p0": p0.clone(), "c": c.clone(), "seconds": time.perf_counter() - t_all,
+           "E_c": relative_error_c(prev, z_prev, c_true_fine)}
+    prev.close()
+    return out
