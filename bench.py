@@ -68,6 +68,124 @@ def cpu_baseline(nt_sample: int, K: int) -> dict:
                       f"512x512 grid, K={K}, {nt_sample} time samples ({dt:.1f} s)"}
 
 
+def checkpointed(plan, wl, c, p0, y, w, evaluation_ms, s=64):
+    """The same evaluation with checkpoints every s steps and segment recompute."""
+    import torch
+    g = wl.grid
+    ws = plan.workspace(s)
+    data = torch.empty(plan.data_shape, dtype=torch.float32, device="cuda")
+    resid = torch.empty_like(data)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gp = torch.empty(plan.field_shape, dtype=torch.float32, device="cuda")
+    gc = torch.empty((g.ny, g.nx), dtype=torch.float32, device="cuda")
+
+    def ev():
+        plan.forward(c, p0, data, ws, ckpt_every=s, record=True)
+        plan.misfit(data, y, w, resid, J)
+        plan.adjoint_gradient(c, p0, resid, gp, gc, ws)
+
+    ev()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ev()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    pts = wl.K * g.nx * g.ny * g.nt
+    return {"ckpt_every": s, "ms_per_step": 1000.0 * dt, "value": pts / dt, "unit": "grid-pt-steps/s",
+            "workspace_GB": round(plan.workspace_size(s) / 1e9, 2),
+            "store_all_workspace_GB": round(plan.workspace_size(0) / 1e9, 2),
+            "slowdown_vs_store_all": round(1000.0 * dt / evaluation_ms, 3)}
+
+
+def batch_w3(evals: int):
+    """32 independent problems (grids 128/192/256, K 1/2/4, 1000-2000 steps,
+    seed 4000), `evals` objective+gradient evaluations each: one batched call
+    per round against the same work run problem by problem."""
+    import torch
+    from paper_2505_08482_amd import pat, tune
+    rng = np.random.default_rng(4000)
+    jobs = []
+    for i in range(32):
+        n = int(rng.choice([128, 192, 256]))
+        K = int(rng.choice([1, 2, 4]))
+        nt = int(rng.integers(1000, 2001))
+        wl = I.config2(n=n, K=K, nt=nt)
+        c_true, p0 = I.phantoms(wl, 4, case=i)
+        plan = pat.Plan(wl.grid, K, wl.sensors)
+        plan.set_tile(tune.tile_for(n, K))
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+        j = {"plan": plan, "c": T(np.full_like(c_true, 1500.0)), "p0": T(p0), "ws": plan.workspace(0),
+             "data": torch.empty(plan.data_shape, device="cuda"), "w": T(np.full(K, 100.0))}
+        plan.forward(T(c_true), j["p0"], j["data"], j["ws"], record=False)
+        j["y"] = j["data"].clone()
+        j["resid"] = torch.empty_like(j["data"])
+        j["J"] = torch.zeros(1, dtype=torch.float64, device="cuda")
+        j["g_p0"] = torch.empty(plan.field_shape, device="cuda")
+        j["g_c"] = torch.empty((n, n), device="cuda")
+        jobs.append(j)
+    pts = sum(j["plan"].K * j["plan"].grid.nx * j["plan"].grid.ny * j["plan"].grid.nt for j in jobs) * evals
+
+    def sequential():
+        for j in jobs:
+            p = j["plan"]
+            p.forward(j["c"], j["p0"], j["data"], j["ws"], record=True)
+            p.misfit(j["data"], j["y"], j["w"], j["resid"], j["J"])
+            p.adjoint_gradient(j["c"], j["p0"], j["resid"], j["g_p0"], j["g_c"], j["ws"])
+
+    sequential()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(evals):
+        sequential()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    ns = tune.streams_for(jobs, label="w3_seed4000")
+    t = time.perf_counter()
+    for _ in range(evals):
+        pat.batch_gradient(jobs, ns)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t
+    for j in jobs:
+        j["plan"].close()
+    return {"problems": 32, "evals_each": evals, "streams": ns,
+            "tiles": sorted({(j["plan"].grid.nx, j["plan"].K) for j in jobs}).__len__(),
+            "batched_value": pts / t_bat, "sequential_value": pts / t_seq, "unit": "grid-pt-steps/s",
+            "speedup": round(t_seq / t_bat, 3), "seconds_batched": round(t_bat, 3),
+            "seconds_sequential": round(t_seq, 3)}
+
+
+def time_to_solution(wl_fine, c_true, y_fine, w, iters: int, target: float = 2.0):
+    """Multigrid 128 -> 256 -> 512 reconstruction (K datasets, c in [1400, 1600],
+    p0 >= 0): wall time and iterations until E_c over the mask <= target %."""
+    import torch
+    from paper_2505_08482_amd import recon
+    levels = [I.config3_level(128, K=wl_fine.K), I.config3_level(256, K=wl_fine.K), wl_fine]
+    log = []
+    t0 = time.perf_counter()
+    reached = {}
+
+    def cb(msg):
+        log.append(msg)
+
+    out = recon.multigrid(levels, y_fine, wl_fine.grid.dt, w, c_true, iters=iters, log=cb)
+    total = time.perf_counter() - t0
+    # the target is judged on the finest level (E_c of coarse levels is measured
+    # against the resampled truth and is only reported)
+    elapsed = sum(lv.seconds for lv in out["levels"][:-1])
+    fine = out["levels"][-1]
+    its_before = sum(lv.iters for lv in out["levels"][:-1])
+    for i, (e, tt) in enumerate(zip(fine.E_c, fine.t)):
+        if e <= target:
+            reached = {"level": fine.n, "iteration_at_level": i + 1, "iterations_total": its_before + i + 1,
+                       "seconds": round(elapsed + tt, 2)}
+            break
+    return {"target_E_c_percent": target, "reached": reached or None, "final_E_c_percent": round(out["E_c"], 3),
+            "total_seconds": round(total, 2),
+            "levels": [{"n": lv.n, "iters": lv.iters, "evals": lv.evals, "seconds": round(lv.seconds, 2),
+                        "E_c_first": round(lv.E_c[0], 3) if lv.E_c else None,
+                        "E_c_last": round(lv.E_c[-1], 3) if lv.E_c else None} for lv in out["levels"]]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +197,10 @@ def main() -> int:
     ap.add_argument("--trace-every", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the checkpointed, batch and time-to-solution measurements")
+    ap.add_argument("--batch-evals", type=int, default=5)
+    ap.add_argument("--tts-iters", type=int, default=40)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -179,6 +301,14 @@ def main() -> int:
         "passes": passes,
         "J": float(J.item()),
     }
+    if not args.no_extras:
+        for name, fn in (("checkpointed", lambda: checkpointed(plan, wl, c, t_p0, y, w, evaluation_ms=ms)),
+                         ("batch", lambda: batch_w3(args.batch_evals)),
+                         ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters))):
+            try:
+                out[name] = fn()
+            except Exception as e:   # an extra must never cost the main line
+                out[name] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, wl.K)
     print(json.dumps(out), flush=True)

@@ -139,6 +139,40 @@ int pat_lbfgs_direction(int64_t n, const float* g, int32_t npairs, const float* 
  * with npairs = 0). */
 int pat_dot(int64_t n, const float* a, const float* b, double* out, void* scratch, void* stream);
 
+/* Column-pass tile width of a plan (power-of-two grids): 0 = the default for
+ * the transform length, 8 = eight adjacent columns per block.  A tuning knob
+ * (results are identical); captured step graphs of the plan are discarded
+ * when it changes.  PAT_EINVAL for other values. */
+int pat_plan_set_tile(pat_plan* plan, int32_t col_tile);
+
+/* One independent problem of a batch: everything a forward + misfit +
+ * adjoint evaluation needs (as for pat_forward / pat_misfit /
+ * pat_adjoint_gradient with store-all history, ckpt_every = 0). */
+typedef struct pat_problem {
+  pat_plan* plan;
+  const float* c;      /* [ny][nx] */
+  const float* p0;     /* [K][ny][nx] */
+  const float* y;      /* [K][nt][m] observed traces */
+  const float* w;      /* [K] weights 1/sigma_i */
+  float* data;         /* [K][nt][m] out: f(p0, c) */
+  float* resid;        /* [K][nt][m] out: w^2 (f - y) */
+  double* J;           /* device scalar out: eq. (4) data term */
+  float* g_p0;         /* [K][ny][nx] out */
+  float* g_c;          /* [ny][nx] out */
+  void* ws;            /* workspace of pat_workspace_size(plan, 0) bytes */
+  size_t ws_bytes;
+} pat_problem;
+
+/* Objective and gradient (eqs. (4)-(9)) of `nprob` independent problems of
+ * any sizes at once: the problems are spread over `nstreams` (1..16) internal
+ * streams (longest first, onto the least-loaded stream) and advanced in
+ * interleaved runs of time steps, each replayed from the problem's captured
+ * step graphs, so that small problems share the GPU.  Ordered after the work
+ * queued on `stream`; `stream` waits for all of it.  Every problem gets
+ * exactly the bits that it gets alone.  Each problem needs its own plan and
+ * workspace (PAT_EINVAL otherwise). */
+int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams, void* stream);
+
 /* Kernel timing (diagnostics).  Kinds of fused pass, in time-step order:
  * forward column GRAD, row U, column DIV, row RHO; adjoint column SUMM, row
  * RHO, column GRAD, row U. */

@@ -45,10 +45,10 @@ __device__ __forceinline__ int phys(int i) { return i + (i >> 3); }
 // holds TC columns x 16/TC rows, spread over all 32 banks by a pitch of
 // 4 (mod 16) complex for TC = 4, 2 (mod 16) for TC = 8, odd for TC = 16.
 template <int N> struct Lds { static constexpr int P = N + N / 8 + 2; };
-template <int N> struct LdsCol {
+template <int N, int TC> struct LdsCol {
   static constexpr int base = N + N / 8;
-  static constexpr int want = Cfg<N>::TC == 4 ? 4 : (Cfg<N>::TC == 8 ? 2 : 1);
-  static constexpr int P = Cfg<N>::TC >= 16 ? (base | 1) : base + ((16 + want - base % 16) % 16);
+  static constexpr int want = TC == 4 ? 4 : (TC == 8 ? 2 : 1);
+  static constexpr int P = TC >= 16 ? (base | 1) : base + ((16 + want - base % 16) % 16);
 };
 
 // One register-resident Stockham stage on NV transforms at once (shared barriers).
@@ -655,12 +655,13 @@ __global__ __launch_bounds__(64) void k_adj_final(Tables tb, const float* __rest
 // ===========================================================================
 // Column pass (transform length NY = N), nx/2 folded columns, TC per block
 // ===========================================================================
-template <int N, int MODE>
-__global__ __launch_bounds__(Cfg<N>::TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
+// TC: columns per block (the default Cfg<N>::TC, or a width picked by the tuner).
+template <int N, int MODE, int TC = Cfg<N>::TC>
+__global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
                                                                 float2* __restrict__ SB, float scale,
                                                                 int32_t* __restrict__ step, int32_t delta) {
   if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;   // first pass of a step
-  constexpr int T = Cfg<N>::T, TC = Cfg<N>::TC, P = LdsCol<N>::P;
+  constexpr int T = Cfg<N>::T, P = LdsCol<N, TC>::P;
   static_assert((TC == 4 && P % 16 == 4) || (TC == 8 && P % 16 == 2) || (TC >= 16 && P % 2 == 1),
                 "column pitch");
   constexpr bool TWO_IN = MODE != COL_GRAD1;

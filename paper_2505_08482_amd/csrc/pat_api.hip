@@ -78,6 +78,7 @@ struct pat_plan {
   pat_grid g;
   int K = 0, m = 0, nh = 0;
   bool fast = false;         // register-resident power-of-two passes (folded spectra)
+  int col_tile = 0;          // column-pass tile width: 0 = default for the length, or 8
   int nhs = 0;               // spectrum row pitch: nx/2 (fast, folded) or nx/2 + 1
   void* dev = nullptr;       // one allocation for every table
   Tables tb{};
@@ -167,9 +168,8 @@ template <int NX>
 int frows_blocks(const pat_plan* p) {
   return p->K * ((p->g.ny + fast::RowF<NX>::ROWS - 1) / fast::RowF<NX>::ROWS);
 }
-template <int NY>
-int fcols_blocks(const pat_plan* p) {
-  return p->K * ((p->g.nx / 2 + fast::Cfg<NY>::TC - 1) / fast::Cfg<NY>::TC);
+int fcols_blocks(const pat_plan* p, int TC) {
+  return p->K * ((p->g.nx / 2 + TC - 1) / TC);
 }
 
 int launch_fwd_init(const pat_plan* p, hipStream_t st, const float* c, const float* p0, float* rx, float* ry,
@@ -264,10 +264,14 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
   TraceScope ts(kind, st);
   if (p->fast) {
     switch (p->g.ny) {
-#define X(N)                                                                                                     \
-  case N:                                                                                                        \
-    hipLaunchKernelGGL((fast::k_col<N, MODE>), dim3(fcols_blocks<N>(p)), dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), \
-                       0, st, p->tb, SA, SB, scale, step, delta);                                                \
+#define X(N)                                                                                                   \
+  case N:                                                                                                      \
+    if (p->col_tile == 8)                                                                                      \
+      hipLaunchKernelGGL((fast::k_col<N, MODE, 8>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st, \
+                         p->tb, SA, SB, scale, step, delta);                                                   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((fast::k_col<N, MODE>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),                      \
+                         dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), 0, st, p->tb, SA, SB, scale, step, delta);  \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -526,6 +530,101 @@ void pml_axis(const pat_grid& g, int n, std::vector<float>& a, std::vector<float
     a2[i] = (float)(fa * fa);
     as2[i] = (float)(fs * fs);
     wf[i] = (float)(fs - 0.5 * fs * fs);
+  }
+}
+
+}  // namespace
+
+namespace {
+
+// ----------------------------------------------------------------------------
+// Batch execution of independent problems on a pool of internal streams
+// ----------------------------------------------------------------------------
+std::vector<hipStream_t> g_pool;   // created on first use, never destroyed (process lifetime)
+
+int pool_streams(int n) {
+  while ((int)g_pool.size() < n) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PAT_EHIP;
+    g_pool.push_back(s);
+  }
+  return PAT_OK;
+}
+
+// One problem's objective + gradient as a sequence of enqueueable units.
+struct BatchJob {
+  pat_problem pr;
+  Layout L;
+  FwdArgs f;
+  AdjArgs a;
+  int phase = 0;     // 0 fwd prologue, 1 fwd steps, 2 misfit + adj prologue, 3 adj steps, 4 closing, 5 done
+  int next = 0;      // next step index of the current phase
+  double cost = 0;   // K * nx * ny * nt (for the schedule)
+  int stream = 0;
+};
+
+int job_unit(BatchJob& j, hipStream_t st) {
+  pat_plan* p = j.pr.plan;
+  const pat_grid& g = p->g;
+  auto fbody = [](pat_plan* pp, hipStream_t s2, const FwdArgs& aa, int cnt) { return fwd_steps(pp, s2, aa, cnt); };
+  auto abody = [](pat_plan* pp, hipStream_t s2, const AdjArgs& aa, int cnt) { return adj_steps(pp, s2, aa, cnt); };
+  switch (j.phase) {
+    case 0:
+      PAT_TRY(set_ctl(st, j.f.ctl, 1 | 4, -1, 0, 0));
+      PAT_TRY(launch_fwd_init(p, st, j.pr.c, j.pr.p0, j.f.rx, j.f.ry, j.f.hist_base, j.f.dpart, j.f.SA));
+      j.phase = 1;
+      j.next = 0;
+      return PAT_OK;
+    case 1: {
+      const int steps = g.nt - 1;
+      const int cnt = std::min(kChunk, steps - j.next);
+      if (cnt > 0) PAT_TRY(run_steps(p, st, j.f, cnt, 1, fbody));
+      j.next += std::max(cnt, 0);
+      if (j.next >= steps) j.phase = 2;
+      return PAT_OK;
+    }
+    case 2: {
+      const int64_t rows = (int64_t)p->K * g.nt;
+      hipLaunchKernelGGL(k_sensor_finalize, dim3(grid_blocks(rows * p->m)), dim3(256), 0, st, j.f.dpart, j.pr.data,
+                         rows, p->m);
+      PAT_TRY(last_error());
+      const int64_t per_k = (int64_t)g.nt * p->m;
+      hipLaunchKernelGGL(k_misfit, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, j.pr.data, j.pr.y, j.pr.w, j.pr.resid,
+                         p->red, per_k, p->K);
+      PAT_TRY(last_error());
+      hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, st, p->red, RED_BLOCKS, j.pr.J, 0.5);
+      PAT_TRY(last_error());
+      PAT_TRY(fill_zero(st, j.a.uhx, j.L.F));
+      PAT_TRY(fill_zero(st, j.a.uhy, j.L.F));
+      PAT_TRY(fill_zero(st, j.a.rhx, j.L.F));
+      PAT_TRY(fill_zero(st, j.a.rhy, j.L.F));
+      PAT_TRY(fill_zero(st, j.a.gck, j.L.F));
+      PAT_TRY(fill_zero(st, j.a.SC, j.L.Sp));
+      PAT_TRY(fill_zero(st, j.a.SD, j.L.Sp));
+      PAT_TRY(set_ctl(st, j.a.ctl, 2 | 4, 0, g.nt, 0));
+      j.phase = 3;
+      j.next = g.nt - 1;
+      return PAT_OK;
+    }
+    case 3: {
+      const int cnt = std::min(kChunk, j.next);
+      if (cnt > 0) PAT_TRY(run_steps(p, st, j.a, cnt, 2, abody));
+      j.next -= std::max(cnt, 0);
+      if (j.next < 1) j.phase = 4;
+      return PAT_OK;
+    }
+    case 4: {
+      const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
+      PAT_TRY(launch_col<COL_SUMM>(p, st, j.a.SC, j.a.SD, (float)(g.dt / g.rho0 * nrm), nullptr, 0));
+      PAT_TRY(launch_adj_final(p, st, j.pr.c, j.pr.p0, j.pr.resid, j.a.rhx, j.a.rhy, j.a.gck, j.pr.g_p0, j.a.SC));
+      const int64_t npix = (int64_t)g.ny * g.nx;
+      hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, j.a.gck, j.pr.g_c, p->K, npix);
+      PAT_TRY(last_error());
+      j.phase = 5;
+      return PAT_OK;
+    }
+    default:
+      return PAT_OK;
   }
 }
 
@@ -907,6 +1006,97 @@ int pat_lbfgs_direction(int64_t n, const float* g, int32_t np, const float* cons
     PAT_TRY(last_error());
   }
   return PAT_OK;
+}
+
+int pat_plan_set_tile(pat_plan* p, int32_t col_tile) {
+  if (!p || (col_tile != 0 && col_tile != 8)) return PAT_EINVAL;
+  if (col_tile != p->col_tile) {   // captured graphs hold the old kernels
+    for (auto& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
+    p->graphs.clear();
+    p->col_tile = col_tile;
+  }
+  return PAT_OK;
+}
+
+int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams, void* stream) {
+  if (nprob <= 0 || !probs || nstreams <= 0 || nstreams > 16) return PAT_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<BatchJob> jobs((size_t)nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const pat_problem& pr = probs[i];
+    if (!pr.plan || !pr.c || !pr.p0 || !pr.y || !pr.w || !pr.data || !pr.resid || !pr.J || !pr.g_p0 || !pr.g_c ||
+        !pr.ws)
+      return PAT_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (probs[j].plan == pr.plan || probs[j].ws == pr.ws) return PAT_EINVAL;   // one job per plan and workspace
+    BatchJob& jb = jobs[i];
+    jb.pr = pr;
+    pat_plan* p = pr.plan;
+    jb.L = make_layout(p, 0);
+    if (pr.ws_bytes < jb.L.total) return PAT_EWORKSPACE;
+    void* ws = pr.ws;
+    jb.f.c = pr.c;
+    jb.f.ux = at<float>(ws, jb.L.ux); jb.f.uy = at<float>(ws, jb.L.uy);
+    jb.f.rx = at<float>(ws, jb.L.rx); jb.f.ry = at<float>(ws, jb.L.ry);
+    jb.f.SA = at<float2>(ws, jb.L.SA); jb.f.SB = at<float2>(ws, jb.L.SB);
+    jb.f.hist_base = at<float>(ws, jb.L.hist);
+    jb.f.dpart = at<float>(ws, jb.L.dpart);
+    jb.f.ctl = at<StepCtl>(ws, jb.L.ctl);
+    jb.a.c = pr.c;
+    jb.a.hist_base = jb.f.hist_base;
+    jb.a.resid = pr.resid;
+    jb.a.uhx = at<float>(ws, jb.L.uhx); jb.a.uhy = at<float>(ws, jb.L.uhy);
+    jb.a.rhx = at<float>(ws, jb.L.rhx); jb.a.rhy = at<float>(ws, jb.L.rhy); jb.a.gck = at<float>(ws, jb.L.gck);
+    jb.a.SC = at<float2>(ws, jb.L.SC); jb.a.SD = at<float2>(ws, jb.L.SD);
+    jb.a.ctl = jb.f.ctl;
+    jb.cost = (double)p->K * p->g.nx * p->g.ny * p->g.nt;
+    p->recorded = false;
+  }
+  const int ns = std::min(nstreams, nprob);
+  PAT_TRY(pool_streams(ns));
+  // schedule: longest problems first, each onto the least-loaded stream
+  std::vector<int> order((size_t)nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return jobs[x].cost > jobs[y].cost; });
+  std::vector<double> load((size_t)ns, 0.0);
+  for (int i : order) {
+    const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    jobs[i].stream = s;
+    load[s] += jobs[i].cost;
+  }
+  // fork: every internal stream waits for the work already queued on the caller's stream
+  hipEvent_t fork;
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return PAT_EHIP;
+  std::vector<hipEvent_t> done((size_t)ns, nullptr);
+  int status = PAT_OK;
+  if (hipEventRecord(fork, st) != hipSuccess) status = PAT_EHIP;
+  for (int s = 0; s < ns && status == PAT_OK; ++s)
+    if (hipStreamWaitEvent(g_pool[s], fork, 0) != hipSuccess) status = PAT_EHIP;
+  // round robin over the problems, one unit each, until all are done
+  bool left = true;
+  while (status == PAT_OK && left) {
+    left = false;
+    for (int i : order) {
+      BatchJob& jb = jobs[i];
+      if (jb.phase >= 5) continue;
+      status = job_unit(jb, g_pool[jb.stream]);
+      if (status != PAT_OK) break;
+      left = left || jb.phase < 5;
+    }
+  }
+  // join: the caller's stream waits for every internal stream
+  for (int s = 0; s < ns; ++s) {
+    if (hipEventCreateWithFlags(&done[s], hipEventDisableTiming) != hipSuccess) {
+      status = PAT_EHIP;
+      continue;
+    }
+    if (hipEventRecord(done[s], g_pool[s]) != hipSuccess || hipStreamWaitEvent(st, done[s], 0) != hipSuccess)
+      status = PAT_EHIP;
+  }
+  (void)hipEventDestroy(fork);
+  for (auto e : done)
+    if (e) (void)hipEventDestroy(e);
+  return status;
 }
 
 int pat_trace_start(int32_t every) {

@@ -22,7 +22,7 @@ EXPORTS = (
     "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_misfit",
     "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_time_interp",
     "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_dot", "pat_status_string",
-    "pat_trace_start", "pat_trace_stop", "pat_trace_read",
+    "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_batch_gradient",
 )
 
 PASS_KINDS = ("fwd_col_grad", "fwd_row_u", "fwd_col_div", "fwd_row_rho",
@@ -33,6 +33,12 @@ class PatError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {status_string(status)} ({status})")
         self.status = status
+
+
+class pat_problem(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("plan", "c", "p0", "y", "w", "data", "resid", "J", "g_p0", "g_c", "ws")] + \
+        [("ws_bytes", ctypes.c_size_t)]
 
 
 class pat_grid(ctypes.Structure):
@@ -72,6 +78,8 @@ def lib() -> ctypes.CDLL:
     L.pat_trace_start.argtypes = [i32]
     L.pat_trace_stop.argtypes = []
     L.pat_trace_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
+    L.pat_plan_set_tile.argtypes = [vp, i32]
+    L.pat_batch_gradient.argtypes = [i32, vp, i32, vp]
     L.pat_status_string.argtypes = [ctypes.c_int]
     L.pat_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -155,6 +163,10 @@ class Plan:
     @property
     def data_shape(self):
         return (self.K, self.grid.nt, self.m)
+
+    def set_tile(self, col_tile: int):
+        """Column-pass tile width (0 = default, 8); results do not change."""
+        _check(lib().pat_plan_set_tile(self._h, int(col_tile)), "pat_plan_set_tile")
 
     def workspace_size(self, ckpt_every: int = 0) -> int:
         b = ctypes.c_size_t()
@@ -252,3 +264,29 @@ def trace_read():
         _check(lib().pat_trace_read(i, ctypes.byref(n), ctypes.byref(ms)), "pat_trace_read")
         out[name] = (n.value, ms.value)
     return out
+
+
+def batch_gradient(jobs, nstreams: int = 8):
+    """Objective + gradient of independent problems at once.  ``jobs``: list of
+    dicts with keys plan, c, p0, y, w, data, resid, J, g_p0, g_c, ws (tensors as
+    for the single-problem calls; store-all workspaces)."""
+    arr = (pat_problem * len(jobs))()
+    for i, j in enumerate(jobs):
+        plan = j["plan"]
+        g = plan.grid
+        N = g.ny * g.nx
+        nd = plan.K * g.nt * plan.m
+        arr[i].plan = plan._h.value
+        arr[i].c = _f32(j["c"], N, "c")
+        arr[i].p0 = _f32(j["p0"], plan.K * N, "p0")
+        arr[i].y = _f32(j["y"], nd, "y")
+        arr[i].w = _f32(j["w"], plan.K, "w")
+        arr[i].data = _f32(j["data"], nd, "data")
+        arr[i].resid = _f32(j["resid"], nd, "resid")
+        arr[i].J = _ptr(j["J"])
+        arr[i].g_p0 = _f32(j["g_p0"], plan.K * N, "g_p0")
+        arr[i].g_c = _f32(j["g_c"], N, "g_c")
+        arr[i].ws = _ptr(j["ws"])
+        arr[i].ws_bytes = j["ws"].numel()
+    _check(lib().pat_batch_gradient(len(jobs), ctypes.cast(arr, ctypes.c_void_p), int(nstreams), _stream()),
+           "pat_batch_gradient")

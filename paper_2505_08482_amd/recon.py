@@ -36,6 +36,7 @@ class LevelResult:
     J: List[float]
     seconds: float
     E_c: List[float]
+    t: List[float]          # seconds since the start of the level, per iteration
 
 
 class Problem:
@@ -211,16 +212,18 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
             pat.prolong(c_true_fine.reshape(1, *c_true_fine.shape).contiguous(), ctf)
             ct = ctf[0]
         Ec = []
+        Ts = []
         t0 = time.perf_counter()
 
         def cb(it, z, J):
             Ec.append(relative_error_c(prob, z, ct))
+            Ts.append(time.perf_counter() - t0)
             if log:
                 log(f"level {g.nx}: iter {it + 1} J {J:.6e} E_c {Ec[-1]:.3f} %")
 
         z, J, hist, nit = projected_lbfgs(prob, z0, iters, memory=memory, callback=cb)
         torch.cuda.synchronize()
-        results.append(LevelResult(g.nx, nit, prob.evals, hist, time.perf_counter() - t0, Ec))
+        results.append(LevelResult(g.nx, nit, prob.evals, hist, time.perf_counter() - t0, Ec, Ts))
         z_prev, prev = z, prob
     x = z_prev * prev.scale
     p0, c = prev.split(x)
