@@ -16,6 +16,7 @@ on a bounded sample of the same workload (few time steps).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,11 +31,66 @@ from paper_2505_08482_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per grid point and launch of each fused pass (float32 state,
-# half spectra along x, c^2 amortised over the K datasets).
-PASS_BYTES = {
-    "fwd_col_grad": 12.0, "fwd_row_u": 32.0, "fwd_col_div": 16.0, "fwd_row_rho": 32.5,
-    "adj_col_summ": 12.0, "adj_row_rho": 33.5, "adj_col_grad": 16.0, "adj_row_u": 32.0,
-}
+# half spectra along x count 4 B/pt, c amortised over the K datasets).  The
+# adjoint density pass adds the g_c terms of ADJ_KB datasets per block, so the
+# g_c slice is read and written once per ADJ_KB datasets: 8 / ADJ_KB B/pt.
+ADJ_KB = 4      # datasets per block of that pass at K >= 4
+
+
+def pass_bytes(K: int) -> dict:
+    kb = ADJ_KB if K >= 4 else (2 if K >= 2 else 1)
+    c_amort = 4.0 / K
+    return {
+        # r spectrum 4; w 2 spectra 8
+        "fwd_col_grad": 12.0,
+        # r 2 spectra 8 + u_x, u_y 8; w u_x, u_y 8 + 2 spectra 8
+        "fwd_row_u": 32.0,
+        # r 2 spectra 8; w 2 spectra 8
+        "fwd_col_div": 16.0,
+        # r 2 spectra 8 + rho_x, rho_y 8 + c; w rho_x, rho_y 8 + history p 4 + spectrum of p 4
+        "fwd_row_rho": 32.0 + c_amort,
+        # r 2 spectra 8; w 1 spectrum 4
+        "adj_col_summ": 12.0,
+        # r spectrum 4 + rho^ 8 + history p 4 + c + g_c 8/kb; w rho^ 8 + g_c + 2 spectra 8
+        "adj_row_rho": 32.0 + c_amort + 8.0 / kb,
+        # r 2 spectra 8; w 2 spectra 8
+        "adj_col_grad": 16.0,
+        # r 2 spectra 8 + u^ 8; w u^ 8 + 2 spectra 8
+        "adj_row_u": 32.0,
+    }
+
+
+PASS_BYTES = pass_bytes(8)
+
+# Measured HBM bytes per launch of the pass kinds (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by what the same counters read for a plain copy of known
+# size), valid only for the kernel sources they were taken on.
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_08482_amd", "traffic.json")
+KERNEL_SOURCES = ("fast_kernels.hpp", "wave_kernels.hpp", "fft_lds.hpp", "vec_kernels.hpp", "pat_api.hip")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(os.path.dirname(TRAFFIC_FILE), "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind: str, wl_name: str):
+    """Bytes per launch of pass ``kind`` at workload ``wl_name`` from the stored
+    counter readings, or None when they are missing or the kernels changed."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_digest() or t.get("workload") != wl_name:
+        return None
+    e = t.get("passes", {}).get(kind)
+    if not e:
+        return None
+    return e["fetch_kib"] * 1024.0 * t["fetch_scale"] + e["write_kib"] * 1024.0 * t["write_scale"]
 STEP_BYTES = sum(PASS_BYTES.values())   # per grid point and time step, forward + adjoint
 
 
@@ -252,8 +308,8 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = 1000.0 * wall / args.steps          # wall clock between the two synchronizations
-    # Per-pass durations: HIP events around sampled launches of every pass kind,
-    # on the stream they run on.  Event records cannot sit inside the captured
+    # Per-pass durations: start/stop HIP events attached to sampled dispatches of
+    # every pass kind, on the stream they run on.  Events cannot sit inside the captured
     # step graphs, so this evaluation (right after the timed ones, same inputs
     # and launch shapes) launches its kernels one by one.
     pat.trace_start(args.trace_every)
@@ -264,15 +320,19 @@ def main() -> int:
     value = pts / (ms / 1000.0)
 
     tr = pat.trace_read()
+    PB = pass_bytes(wl.K)
+    # measured bytes of the dominant pass (set below once it is known)
+    tb = None
     shares = {k: v[1] / max(v[0], 1) for k, v in tr.items()}   # average launch duration, ms
     # every pass kind runs nt-1 times per evaluation: the longest average is the dominant one
-    dom = max(PASS_BYTES, key=lambda k: shares[k])
+    dom = max(PB, key=lambda k: shares[k])
+    tb = measured_traffic(dom, wl.name)
     avg_ms = shares[dom]
     units = wl.K * g.nx * g.ny
-    achieved = PASS_BYTES[dom] * units / (avg_ms / 1000.0) / 1e9
+    achieved = PB[dom] * units / (avg_ms / 1000.0) / 1e9
     passes = {k: {"avg_us": round(1000.0 * shares[k], 2), "timed_launches": tr[k][0],
-                  "alg_GBps": round(PASS_BYTES[k] * units / (shares[k] / 1000.0) / 1e9, 1) if shares[k] > 0 else None}
-              for k in PASS_BYTES}
+                  "alg_GBps": round(PB[k] * units / (shares[k] / 1000.0) / 1e9, 1) if shares[k] > 0 else None}
+              for k in PB}
     out = {
         "metric": "grid-pt-steps/s fwd+adjoint at 512^2 x 8 datasets",
         "value": value,
@@ -291,13 +351,16 @@ def main() -> int:
                    "history": "store-all" if args.ckpt == 0 else f"checkpoint every {args.ckpt}",
                    "step": "recorded forward + misfit + adjoint gradient (g_p0 for all K, g_c)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-                     "avg_us": round(1000.0 * avg_ms, 2), "bytes_per_point": PASS_BYTES[dom],
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": round(tb / (avg_ms / 1000.0) / 1e9, 1) if tb else None,
+                     "traffic_bytes_per_launch": tb, "algorithmic_bytes_per_launch": PB[dom] * units,
+                     "kernel": dom,
+                     "avg_us": round(1000.0 * avg_ms, 2), "bytes_per_point": PB[dom],
                      "units_per_launch": units,
-                     "timing": "HIP events on the launch stream, every %d-th launch of each pass, one evaluation "
-                               "launched kernel by kernel right after the timed (graph-replayed) ones"
-                               % args.trace_every},
-        "step_alg_GBps": round(STEP_BYTES * pts / (ms / 1000.0) / 1e9, 1),
+                     "timing": "HIP start/stop events attached to the kernel dispatch (hipExtLaunchKernelGGL) "
+                               "on the launch stream, every %d-th launch of each pass, in one evaluation launched "
+                               "kernel by kernel right after the timed (graph-replayed) ones" % args.trace_every},
+        "step_alg_GBps": round(sum(PB.values()) * pts / (ms / 1000.0) / 1e9, 1),
         "passes": passes,
         "J": float(J.item()),
     }

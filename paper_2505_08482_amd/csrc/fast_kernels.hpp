@@ -418,28 +418,87 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
   }
 }
 
+// Adjoint row passes that touch g_c run KB datasets per block (one wave per
+// dataset, same rows): each wave leaves its per-pixel g_c term in LDS and the
+// block adds the KB terms in dataset order to one g_c slice per dataset group,
+// so g_c is read and written once per pixel and group instead of once per
+// dataset.  Waves past the last dataset of a partial group compute on a valid
+// dataset (block-uniform barriers) and store nothing.
+template <int N, int KB>
+struct AdjBlk {
+  using RC = RowF<N>;
+  static constexpr int T = RC::T;
+  static constexpr int NR = RC::ROWS * N / (64 * KB);   // reduced pixels per thread
+  int G, kg, ybase, wave, lane, kw, k, grp, q, lane_base, y0, y1;
+  bool act, ok;
+  __device__ __forceinline__ AdjBlk(const Tables& tb) {
+    G = (tb.K + KB - 1) / KB;
+    kg = blockIdx.x % G;
+    ybase = (blockIdx.x / G) * RC::ROWS;
+    wave = threadIdx.x / 64;
+    lane = threadIdx.x % 64;
+    kw = kg * KB + wave;
+    act = kw < tb.K;
+    k = act ? kw : tb.K - 1;
+    grp = lane / T;
+    q = lane % T;
+    lane_base = grp * T;
+    y0 = ybase + 2 * grp;
+    y1 = y0 + 1;
+    ok = y1 < tb.ny;
+  }
+  // g_c slice values of this thread's reduced pixels (prefetch)
+  __device__ __forceinline__ void load_slice(const Tables& tb, const float* __restrict__ gcg, float (&gp)[NR]) const {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const int i = threadIdx.x + j * 64 * KB, r = i / N, x = i % N, y = ybase + r;
+      gp[j] = y < tb.ny ? gcg[((size_t)kg * tb.ny + y) * N + x] : 0.f;
+    }
+  }
+  // gcg[slice kg] = prefetched + sum over the group's datasets of their terms
+  __device__ __forceinline__ void reduce_store(const Tables& tb, float (*D)[RC::ROWS][N], const float (&gp)[NR],
+                                               float* __restrict__ gcg) const {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const int i = threadIdx.x + j * 64 * KB, r = i / N, x = i % N, y = ybase + r;
+      float s = gp[j];
+#pragma unroll
+      for (int w = 0; w < KB; ++w)
+        if (kg * KB + w < tb.K) s += D[w][r][x];
+      if (y < tb.ny) gcg[((size_t)kg * tb.ny + y) * N + x] = s;
+    }
+  }
+};
+
 // adjoint: ph = S^T r^n + (inverse rows of the SUMM spectrum); rh += c^2 ph;
-// gc += (2/c) p^n ph; spectra of (a_x rh_x + i a_y rh_y); rh <- a^2 rh.
-// Every global load (spectra, state, history, sensor injections) is issued
-// before the first transform so that their latencies overlap.
-template <int N>
-__global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restrict__ c,
-                                                const float* __restrict__ hist_base, const float* __restrict__ resid,
-                                                float* __restrict__ rhx, float* __restrict__ rhy,
-                                                float* __restrict__ gck, float2* __restrict__ SA,
-                                                float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
-  PAT_ROW_PROLOGUE(N)
+// g_c += (2/c) p^n ph (summed over the block's datasets); spectra of
+// (a_x rh_x + i a_y rh_y); rh <- a^2 rh.  Every global load (spectra, state,
+// history, g_c slice, sensor injections) is issued before the first transform.
+template <int N, int KB>
+__global__ __launch_bounds__(64 * KB) void k_adj_rho(Tables tb, const float* __restrict__ c,
+                                                     const float* __restrict__ hist_base,
+                                                     const float* __restrict__ resid, float* __restrict__ rhx,
+                                                     float* __restrict__ rhy, float* __restrict__ gcg,
+                                                     float2* __restrict__ SA, float2* __restrict__ SB,
+                                                     const StepCtl* __restrict__ ctl) {
+  using RC = RowF<N>;
+  constexpr int T = RC::T;
+  const AdjBlk<N, KB> b(tb);
+  const int ny = tb.ny, nhf = N / 2, k = b.k, grp = b.grp, q = b.q, y0 = b.y0;
+  const bool ok = b.ok, st = b.ok && b.act;
+  Fft<N> fft;
+  fft.init(tb.tw_x, q);
   const int n = ctl->adj_n;
   const float* p_n = hist_base + (size_t)(n - ctl->hist_first) * tb.K * ny * N;
   const float* resid_n = resid + (size_t)n * tb.m;
-  __shared__ float2 X[RC::G][2][Lds<N>::P];
-  __shared__ float PH[RC::ROWS][N];
-  const bool ok = y1 < ny;
+  __shared__ float2 X[KB][RC::G][2][Lds<N>::P];
+  __shared__ float PH[KB][RC::ROWS][N];
   float2 v[1][8];
-  float orx[2][8], ory[2][8], og[2][8], op[2][8], oc[2][8];
+  float orx[2][8], ory[2][8], op[2][8], oc[2][8];
+  float gp[AdjBlk<N, KB>::NR];
   {
     const float2* A = SA + ((size_t)k * ny + (ok ? y0 : 0)) * nhf;
-    const float2* B = SA + ((size_t)k * ny + (ok ? y1 : 0)) * nhf;
+    const float2* B = SA + ((size_t)k * ny + (ok ? y0 + 1 : 0)) * nhf;
     pack_row<N>(v[0], A, B, q);
   }
 #pragma unroll
@@ -451,11 +510,11 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
       const int x = q + T * m;
       orx[h][m] = rhx[f + x];
       ory[h][m] = rhy[f + x];
-      og[h][m] = gck[f + x];
       op[h][m] = p_n[f + x];
       oc[h][m] = c[(size_t)y * N + x];
     }
   }
+  b.load_slice(tb, gcg, gp);
   float pax[8], pax2[8], pay[2], pay2[2];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -467,10 +526,11 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
     pay[h] = tb.ay[ok ? y0 + h : 0];
     pay2[h] = tb.ay2[ok ? y0 + h : 0];
   }
-  // sensor injections of this block's rows: one pixel per thread (prefetched)
+  // sensor injections of this block's rows for this wave's dataset: one pixel per lane (prefetched)
   const float* rk = resid_n + (size_t)k * tb.nt * tb.m;
+  const int ybase = b.ybase, lane = b.lane;
   const int e0 = tb.s_row_start[ybase], e1 = tb.s_row_start[min(ybase + RC::ROWS, ny)];
-  const int e = e0 + tid;
+  const int e = e0 + lane;
   float inj = 0.f;
   int inj_at = -1;
   if (e < e1) {
@@ -484,24 +544,25 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
     }
     inj_at = (px.row - ybase) * N + px.ix;
   }
-  float2* L1[1] = {X[grp][0]};
+  float(*P)[N] = PH[b.wave];
+  float2* L1[1] = {X[b.wave][grp][0]};
   fft.template run<+1, 1>(v, L1, q);
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    PH[2 * grp][q + T * m] = v[0][m].x;
-    PH[2 * grp + 1][q + T * m] = v[0][m].y;
+    P[2 * grp][q + T * m] = v[0][m].x;
+    P[2 * grp + 1][q + T * m] = v[0][m].y;
   }
   __syncthreads();
-  if (inj_at >= 0) (&PH[0][0])[inj_at] += inj;
+  if (inj_at >= 0) (&P[0][0])[inj_at] += inj;
   if (e1 - e0 > 64) {   // rows crowded with sensors: the remaining pixels, one pass each
-    for (int e2 = e0 + 64 + tid; e2 < e1; e2 += 64) {
+    for (int e2 = e0 + 64 + lane; e2 < e1; e2 += 64) {
       const ScatterPix px = tb.s_pix[e2];
       float acc = 0.f;
       for (int t = 0; t < px.count; ++t) {
         const ScatterTap tp = tb.s_tap[px.start + t];
         acc += tp.w * rk[tp.sensor];
       }
-      (&PH[0][0])[(px.row - ybase) * N + px.ix] += acc;
+      (&P[0][0])[(px.row - ybase) * N + px.ix] += acc;
     }
   }
   __syncthreads();
@@ -514,28 +575,30 @@ __global__ __launch_bounds__(64) void k_adj_rho(Tables tb, const float* __restri
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int x = q + T * m;
-      const float ph = PH[2 * grp + h][x];
+      const float ph = P[2 * grp + h][x];
       const float cv = oc[h][m];
       const float c2 = cv * cv;
       const float nrx = orx[h][m] + c2 * ph;
       const float nry = ory[h][m] + c2 * ph;
-      // 2/c with the hardware reciprocal (1 ulp): the sound-speed sensitivity term
-      const float gnew = og[h][m] + (2.0f * __builtin_amdgcn_rcpf(cv)) * op[h][m] * ph;
-      if (ok) {
-        gck[f + x] = gnew;
+      // this dataset's sound-speed term, 2/c with the hardware reciprocal (1 ulp);
+      // left in place of ph (each lane rereads only its own pixels)
+      P[2 * grp + h][x] = (2.0f * __builtin_amdgcn_rcpf(cv)) * op[h][m] * ph;
+      if (st) {
         rhx[f + x] = pax2[m] * nrx;
         rhy[f + x] = ay2s * nry;
       }
       w[h][m] = make_float2(pax[m] * nrx, ays * nry);
     }
   }
-  float2* L[2] = {X[grp][0], X[grp][1]};
+  __syncthreads();
+  b.reduce_store(tb, PH, gp, gcg);
+  float2* L[2] = {X[b.wave][grp][0], X[b.wave][grp][1]};
   fft.template run<-1, 2>(w, L, q);
-  if (ok) {
+  if (st) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const size_t r = ((size_t)k * ny + y0 + h) * nhf;
-      unpack_store<N>(w[h], q, lane_base, SA + r, SB + r);
+      unpack_store<N>(w[h], q, b.lane_base, SA + r, SB + r);
     }
   }
 }
@@ -610,46 +673,56 @@ __global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx
 }
 
 // closing terms of the adjoint: g_p0 and the initial-state part of g_c
-template <int N>
-__global__ __launch_bounds__(64) void k_adj_final(Tables tb, const float* __restrict__ c, const float* __restrict__ p0,
-                                                  const float* __restrict__ resid0, const float* __restrict__ rhx,
-                                                  const float* __restrict__ rhy, float* __restrict__ gck,
-                                                  float* __restrict__ gp0, const float2* __restrict__ SA) {
-  PAT_ROW_PROLOGUE(N)
-  __shared__ float2 X[RC::G][Lds<N>::P];
-  __shared__ float PH[RC::ROWS][N];
-  const bool ok = y1 < ny;
+// (summed over the block's datasets into the group's g_c slice)
+template <int N, int KB>
+__global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* __restrict__ c,
+                                                       const float* __restrict__ p0, const float* __restrict__ resid0,
+                                                       const float* __restrict__ rhx, const float* __restrict__ rhy,
+                                                       float* __restrict__ gcg, float* __restrict__ gp0,
+                                                       const float2* __restrict__ SA) {
+  using RC = RowF<N>;
+  constexpr int T = RC::T;
+  const AdjBlk<N, KB> b(tb);
+  const int ny = tb.ny, nhf = N / 2, k = b.k, grp = b.grp, q = b.q, y0 = b.y0;
+  const bool ok = b.ok;
+  Fft<N> fft;
+  fft.init(tb.tw_x, q);
+  __shared__ float2 X[KB][RC::G][Lds<N>::P];
+  __shared__ float PH[KB][RC::ROWS][N];
+  float gp[AdjBlk<N, KB>::NR];
+  b.load_slice(tb, gcg, gp);
   float2 v[1][8];
   {
     const float2* A = SA + ((size_t)k * ny + (ok ? y0 : 0)) * nhf;
-    const float2* B = SA + ((size_t)k * ny + (ok ? y1 : 0)) * nhf;
+    const float2* B = SA + ((size_t)k * ny + (ok ? y0 + 1 : 0)) * nhf;
     pack_row<N>(v[0], A, B, q);
   }
-  float2* L1[1] = {X[grp]};
+  float(*P)[N] = PH[b.wave];
+  float2* L1[1] = {X[b.wave][grp]};
   fft.template run<+1, 1>(v, L1, q);
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    PH[2 * grp][q + T * m] = v[0][m].x;
-    PH[2 * grp + 1][q + T * m] = v[0][m].y;
+    P[2 * grp][q + T * m] = v[0][m].x;
+    P[2 * grp + 1][q + T * m] = v[0][m].y;
   }
   __syncthreads();
-  scatter_rows<N, 64>(tb, &PH[0][0], ybase, RC::ROWS, resid0 + (size_t)k * tb.nt * tb.m, tid);
+  scatter_rows<N, 64>(tb, &P[0][0], b.ybase, RC::ROWS, resid0 + (size_t)k * tb.nt * tb.m, b.lane);
   __syncthreads();
-  if (ok) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int y = y0 + h;
-      const size_t f = ((size_t)k * ny + y) * N;
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int x = q + T * m;
-        const float cv = c[(size_t)y * N + x];
-        const float rs = rhx[f + x] + rhy[f + x];
-        gp0[f + x] = PH[2 * grp + h][x] + rs * (0.5f / (cv * cv));
-        gck[f + x] += -(p0[f + x] / (cv * cv * cv)) * rs;
-      }
+    for (int m = 0; m < 8; ++m) {
+      const int x = q + T * m;
+      const float cv = c[(size_t)y * N + x];
+      const float rs = rhx[f + x] + rhy[f + x];
+      if (ok && b.act) gp0[f + x] = P[2 * grp + h][x] + rs * (0.5f / (cv * cv));
+      P[2 * grp + h][x] = -(p0[f + x] / (cv * cv * cv)) * rs;
     }
   }
+  __syncthreads();
+  b.reduce_store(tb, PH, gp, gcg);
 }
 
 // ===========================================================================

@@ -1,6 +1,7 @@
 // pat_api.hip — C ABI (include/pat.h): plans, workspace layout and the time
 // loops of the forward solve and of its adjoint, on top of the fused passes.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -57,20 +58,34 @@ struct Trace {
 };
 Trace g_trace;
 
+// A sampled launch gets the event pair of its slot as the start / stop events
+// of its own dispatch (hipExtLaunchKernelGGL), so the elapsed time between them
+// is the kernel's execution alone, without the queue's dispatch latency.
+hipEvent_t g_launch_ev[2] = {nullptr, nullptr};
+
 struct TraceScope {
-  int slot = -1, kind;
-  hipStream_t st;
-  TraceScope(int kind_, hipStream_t st_) : kind(kind_), st(st_) {
+  TraceScope(int kind, hipStream_t) {
+    g_launch_ev[0] = g_launch_ev[1] = nullptr;
     if (!g_trace.on) return;
     const int64_t s = g_trace.seen[kind]++;
     if (s % g_trace.every != 0 || g_trace.used[kind] >= kTraceCap) return;
-    slot = g_trace.used[kind]++;
-    (void)hipEventRecord(g_trace.ev[((size_t)kind * kTraceCap + slot) * 2], st);
+    const int slot = g_trace.used[kind]++;
+    g_launch_ev[0] = g_trace.ev[((size_t)kind * kTraceCap + slot) * 2];
+    g_launch_ev[1] = g_trace.ev[((size_t)kind * kTraceCap + slot) * 2 + 1];
   }
-  ~TraceScope() {
-    if (slot >= 0) (void)hipEventRecord(g_trace.ev[((size_t)kind * kTraceCap + slot) * 2 + 1], st);
-  }
+  ~TraceScope() { g_launch_ev[0] = g_launch_ev[1] = nullptr; }
 };
+
+// Launch a pass kernel; the launch under a sampled TraceScope carries its events.
+#define PAT_LAUNCH(KERN, GRID, BLOCK, SHM, ST, ...)                                                   \
+  do {                                                                                                \
+    if (g_launch_ev[0]) {                                                                             \
+      hipExtLaunchKernelGGL(KERN, GRID, BLOCK, SHM, ST, g_launch_ev[0], g_launch_ev[1], 0, __VA_ARGS__); \
+      g_launch_ev[0] = g_launch_ev[1] = nullptr;                                                      \
+    } else {                                                                                          \
+      hipLaunchKernelGGL(KERN, GRID, BLOCK, SHM, ST, __VA_ARGS__);                                    \
+    }                                                                                                 \
+  } while (0)
 
 }  // namespace
 
@@ -79,6 +94,8 @@ struct pat_plan {
   int K = 0, m = 0, nh = 0;
   bool fast = false;         // register-resident power-of-two passes (folded spectra)
   int col_tile = 0;          // column-pass tile width: 0 = default for the length, or 8
+  int kb = 1;                // datasets per block of the fast adjoint density / closing passes
+  int gsl = 0;               // g_c partial slices: ceil(K / kb) (fast), K (generic)
   int nhs = 0;               // spectrum row pitch: nx/2 (fast, folded) or nx/2 + 1
   void* dev = nullptr;       // one allocation for every table
   Tables tb{};
@@ -168,6 +185,11 @@ template <int NX>
 int frows_blocks(const pat_plan* p) {
   return p->K * ((p->g.ny + fast::RowF<NX>::ROWS - 1) / fast::RowF<NX>::ROWS);
 }
+// adjoint density / closing passes: one block per (dataset group, ROWS rows)
+template <int NX>
+int fadj_blocks(const pat_plan* p) {
+  return p->gsl * ((p->g.ny + fast::RowF<NX>::ROWS - 1) / fast::RowF<NX>::ROWS);
+}
 int fcols_blocks(const pat_plan* p, int TC) {
   return p->K * ((p->g.nx / 2 + TC - 1) / TC);
 }
@@ -206,7 +228,7 @@ int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2
     switch (p->g.nx) {
 #define X(N)                                                                                                \
   case N:                                                                                                   \
-    hipLaunchKernelGGL(fast::k_fwd_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, ux, uy, SA, SB, ctl); \
+    PAT_LAUNCH(fast::k_fwd_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, ux, uy, SA, SB, ctl); \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -216,7 +238,7 @@ int launch_fwd_u(const pat_plan* p, hipStream_t st, float* ux, float* uy, float2
   switch (p->g.nx) {
 #define X(N)                                                                                                \
   case N:                                                                                                   \
-    hipLaunchKernelGGL(k_fwd_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, ux, uy, SA, SB, ctl); \
+    PAT_LAUNCH(k_fwd_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, ux, uy, SA, SB, ctl); \
     break;
     PAT_SIZE_CASES(X)
 #undef X
@@ -232,7 +254,7 @@ int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx,
     switch (p->g.nx) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL(fast::k_fwd_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, rx, ry,       \
+    PAT_LAUNCH(fast::k_fwd_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, rx, ry,       \
                        hist_base, dpart, SA, SB, ctl);                                                        \
     return last_error();
       PAT_FAST_CASES(X)
@@ -243,7 +265,7 @@ int launch_fwd_rho(const pat_plan* p, hipStream_t st, const float* c, float* rx,
   switch (p->g.nx) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL(k_fwd_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, rx, ry, hist_base, \
+    PAT_LAUNCH(k_fwd_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, rx, ry, hist_base, \
                        dpart, SA, SB, ctl);                                                                   \
     break;
     PAT_SIZE_CASES(X)
@@ -267,10 +289,10 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
 #define X(N)                                                                                                   \
   case N:                                                                                                      \
     if (p->col_tile == 8)                                                                                      \
-      hipLaunchKernelGGL((fast::k_col<N, MODE, 8>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st, \
+      PAT_LAUNCH((fast::k_col<N, MODE, 8>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st, \
                          p->tb, SA, SB, scale, step, delta);                                                   \
     else                                                                                                       \
-      hipLaunchKernelGGL((fast::k_col<N, MODE>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),                      \
+      PAT_LAUNCH((fast::k_col<N, MODE>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),                      \
                          dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), 0, st, p->tb, SA, SB, scale, step, delta);  \
     return last_error();
       PAT_FAST_CASES(X)
@@ -281,7 +303,7 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
   switch (p->g.ny) {
 #define X(N)                                                                                                 \
   case N:                                                                                                    \
-    hipLaunchKernelGGL((k_col<N, MODE>), dim3(cols_blocks<N>(p)), dim3(ColCfg<N>::BLOCK), 0, st, p->tb, SA, \
+    PAT_LAUNCH((k_col<N, MODE>), dim3(cols_blocks<N>(p)), dim3(ColCfg<N>::BLOCK), 0, st, p->tb, SA, \
                        SB, scale, step, delta);                                                              \
     break;
     PAT_SIZE_CASES(X)
@@ -298,8 +320,16 @@ int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const floa
     switch (p->g.nx) {
 #define X(N)                                                                                                   \
   case N:                                                                                                      \
-    hipLaunchKernelGGL(fast::k_adj_rho<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, hist_base,     \
-                       resid, rhx, rhy, gck, SA, SB, ctl);                                                     \
+    switch (p->kb) {                                                                                           \
+      case 8: PAT_LAUNCH((fast::k_adj_rho<N, 8>), dim3(fadj_blocks<N>(p)), dim3(512), 0, st, p->tb, c,  \
+                                 hist_base, resid, rhx, rhy, gck, SA, SB, ctl); break;                          \
+      case 4: PAT_LAUNCH((fast::k_adj_rho<N, 4>), dim3(fadj_blocks<N>(p)), dim3(256), 0, st, p->tb, c,  \
+                                 hist_base, resid, rhx, rhy, gck, SA, SB, ctl); break;                          \
+      case 2: PAT_LAUNCH((fast::k_adj_rho<N, 2>), dim3(fadj_blocks<N>(p)), dim3(128), 0, st, p->tb, c,  \
+                                 hist_base, resid, rhx, rhy, gck, SA, SB, ctl); break;                          \
+      default: PAT_LAUNCH((fast::k_adj_rho<N, 1>), dim3(fadj_blocks<N>(p)), dim3(64), 0, st, p->tb, c,  \
+                                  hist_base, resid, rhx, rhy, gck, SA, SB, ctl); break;                         \
+    }                                                                                                          \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -309,7 +339,7 @@ int launch_adj_rho(const pat_plan* p, hipStream_t st, const float* c, const floa
   switch (p->g.nx) {
 #define X(N)                                                                                                    \
   case N:                                                                                                       \
-    hipLaunchKernelGGL(k_adj_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, hist_base, resid, rhx, \
+    PAT_LAUNCH(k_adj_rho<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, c, hist_base, resid, rhx, \
                        rhy, gck, SA, SB, ctl);                                                                  \
     break;
     PAT_SIZE_CASES(X)
@@ -326,7 +356,7 @@ int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, floa
     switch (p->g.nx) {
 #define X(N)                                                                                                    \
   case N:                                                                                                       \
-    hipLaunchKernelGGL(fast::k_adj_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, uhx, uhy, SA, SB, ctl); \
+    PAT_LAUNCH(fast::k_adj_u<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, uhx, uhy, SA, SB, ctl); \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -336,7 +366,7 @@ int launch_adj_u(const pat_plan* p, hipStream_t st, float* uhx, float* uhy, floa
   switch (p->g.nx) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL(k_adj_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, uhx, uhy, SA, SB, ctl); \
+    PAT_LAUNCH(k_adj_u<N>, dim3(rows_blocks<N>(p)), dim3(256), 0, st, p->tb, uhx, uhy, SA, SB, ctl); \
     break;
     PAT_SIZE_CASES(X)
 #undef X
@@ -351,8 +381,16 @@ int launch_adj_final(const pat_plan* p, hipStream_t st, const float* c, const fl
     switch (p->g.nx) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL(fast::k_adj_final<N>, dim3(frows_blocks<N>(p)), dim3(64), 0, st, p->tb, c, p0, resid0, \
-                       rhx, rhy, gck, gp0, SA);                                                               \
+    switch (p->kb) {                                                                                          \
+      case 8: hipLaunchKernelGGL((fast::k_adj_final<N, 8>), dim3(fadj_blocks<N>(p)), dim3(512), 0, st, p->tb,  \
+                                 c, p0, resid0, rhx, rhy, gck, gp0, SA); break;                                \
+      case 4: hipLaunchKernelGGL((fast::k_adj_final<N, 4>), dim3(fadj_blocks<N>(p)), dim3(256), 0, st, p->tb,  \
+                                 c, p0, resid0, rhx, rhy, gck, gp0, SA); break;                                \
+      case 2: hipLaunchKernelGGL((fast::k_adj_final<N, 2>), dim3(fadj_blocks<N>(p)), dim3(128), 0, st, p->tb,  \
+                                 c, p0, resid0, rhx, rhy, gck, gp0, SA); break;                                \
+      default: hipLaunchKernelGGL((fast::k_adj_final<N, 1>), dim3(fadj_blocks<N>(p)), dim3(64), 0, st, p->tb,  \
+                                  c, p0, resid0, rhx, rhy, gck, gp0, SA); break;                               \
+    }                                                                                                         \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -618,7 +656,7 @@ int job_unit(BatchJob& j, hipStream_t st) {
       PAT_TRY(launch_col<COL_SUMM>(p, st, j.a.SC, j.a.SD, (float)(g.dt / g.rho0 * nrm), nullptr, 0));
       PAT_TRY(launch_adj_final(p, st, j.pr.c, j.pr.p0, j.pr.resid, j.a.rhx, j.a.rhy, j.a.gck, j.pr.g_p0, j.a.SC));
       const int64_t npix = (int64_t)g.ny * g.nx;
-      hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, j.a.gck, j.pr.g_c, p->K, npix);
+      hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, j.a.gck, j.pr.g_c, p->gsl, npix);
       PAT_TRY(last_error());
       j.phase = 5;
       return PAT_OK;
@@ -754,6 +792,10 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   p->nh = nh;
   p->fast = fast_size(nx) && fast_size(ny) && !std::getenv("PAT_GENERIC_KERNELS");
   p->nhs = p->fast ? nx / 2 : nh;
+  // 4 datasets per block: g_c traffic 2 B/pt instead of 8; 8 per block (one
+  // block per CU at 107 KB of LDS) measured no faster at 512^2 x 8
+  p->kb = !p->fast ? 1 : (K >= 4 ? 4 : (K >= 2 ? 2 : 1));
+  p->gsl = (K + p->kb - 1) / p->kb;
   if (hipMalloc(&p->dev, total) != hipSuccess) {
     delete p;
     return PAT_EHIP;
@@ -932,7 +974,7 @@ int pat_adjoint_gradient(pat_plan* p, const float* c, const float* p0, const flo
   PAT_TRY(launch_col<COL_SUMM>(p, st, a.SC, a.SD, (float)(g.dt / g.rho0 * nrm), nullptr, 0));
   PAT_TRY(launch_adj_final(p, st, c, p0, resid, a.rhx, a.rhy, a.gck, g_p0, a.SC));
   const int64_t npix = (int64_t)g.ny * g.nx;
-  hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, a.gck, g_c, p->K, npix);
+  hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, a.gck, g_c, p->gsl, npix);
   return last_error();
 }
 

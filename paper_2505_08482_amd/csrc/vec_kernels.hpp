@@ -30,7 +30,7 @@ __global__ void k_sensor_finalize(const float* __restrict__ part, float* __restr
   }
 }
 
-// g_c = sum_k gck[k]  (fixed order over k)
+// g_c = sum of the K partial slices gck[0..K)  (fixed order)
 __global__ void k_reduce_k(const float* __restrict__ gck, float* __restrict__ gc, int K, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float s = 0.f;

@@ -3,7 +3,8 @@
 * checkpointed history (recompute from checkpoints) gives bit-identical
   gradients to the stored history, including a ragged last segment;
 * a batch of K datasets gives bit-identical data and g_p0 to K single runs,
-  and g_c equal to their sum in the same order;
+  and g_c equal to their sum up to float32 rounding (also for K not a
+  multiple of the datasets per block of the adjoint density pass);
 * oracle parity at 512^2 on a short time axis, and the W1 launch
   configuration (512^2, K = 8, 4000 samples) checked by properties that hold
   at any size: linearity in p0 and the adjoint dot-product identity;
@@ -47,19 +48,23 @@ def test_checkpointed_equals_store_all_bitwise(s):
     assert np.array_equal(a["g_c"], b["g_c"])
 
 
-def test_batch_equals_single_runs_bitwise():
-    wl = _wl(K=4, nt=150)
+@pytest.mark.parametrize("K", [4, 6])
+def test_batch_equals_single_runs_bitwise(K):
+    wl = _wl(K=K, nt=150)
     c, p0, r = _inputs(wl, seed=3)
-    announce("batch K=4 vs singles")
+    announce(f"batch K={K} vs singles")
     full = gpu_forward_adjoint(wl, c, p0, resid32=r)
-    gc_sum = np.zeros_like(full["g_c"])
+    gc_sum = np.zeros(full["g_c"].shape, dtype=np.float64)
     for k in range(wl.K):
         w1 = dataclasses.replace(wl, K=1)
         one = gpu_forward_adjoint(w1, c, p0[k:k + 1], resid32=np.ascontiguousarray(r[k:k + 1]))
         assert np.array_equal(one["data"][0], full["data"][k])
         assert np.array_equal(one["g_p0"][0], full["g_p0"][k])
-        gc_sum = (gc_sum + one["g_c"]).astype(np.float32)
-    assert np.array_equal(gc_sum, full["g_c"])
+        gc_sum = gc_sum + one["g_c"].astype(np.float64)
+    # g_c of a batch adds the datasets' terms at every step (in dataset order)
+    # before accumulating over time; a single run accumulates over time only, so
+    # the float32 sums agree to rounding, not bitwise
+    assert rel_l2(full["g_c"], gc_sum) <= 1e-5
 
 
 def test_oracle_parity_512_short():
@@ -177,3 +182,24 @@ def test_graph_replay_equals_eager_bitwise(ckpt):
             assert np.array_equal(a, b), rep
         _ = (c * 1.0).sum().item()   # unrelated eager work and a synchronisation between replays
     plan.close()
+
+
+def test_traced_launches_equal_plain_and_time_every_pass():
+    """Sampled launches carry dispatch events (extended launch); the results
+    must not change and every pass kind must report a positive duration."""
+    from paper_2505_08482_amd import pat
+    wl = _wl(n=128, K=3, nt=60)
+    c, p0, r = _inputs(wl, seed=5)
+    announce("traced vs plain launches")
+    plain = gpu_forward_adjoint(wl, c, p0, resid32=r)
+    pat.trace_start(3)
+    try:
+        traced = gpu_forward_adjoint(wl, c, p0, resid32=r)
+    finally:
+        pat.trace_stop()
+    tr = pat.trace_read()
+    for key in ("data", "g_p0", "g_c"):
+        assert np.array_equal(plain[key], traced[key])
+    for kind, (n, ms) in tr.items():
+        print(f"[trace] {kind}: {n} launches, {ms / max(n, 1) * 1000:.2f} us")
+        assert n > 0 and ms > 0.0
