@@ -4,14 +4,17 @@ forward solves, the data misfit, K adjoint solves accumulating g_p0 and g_c)
 on the 512^2 x 8-dataset workload, 4000 time samples, float32, one GPU.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--nt 4000] [--ckpt S]
-                    [--no-cpu] [--cpu-steps 20]
+                    [--no-cpu] [--cpu-steps 100]
 
 Prints ONE JSON line.  ``value`` is grid-pt-steps/s = K * N^2 * Nt / (seconds
 per evaluation), inputs resident in HBM.  ``roofline`` is the dominant fused
 pass: algorithmic bytes per launch (bytes per grid point x K N^2) divided by
-its average launch duration, timed with HIP events on its own stream over the
-timed region.  ``cpu_baseline`` times the float64 oracle on this host's cores
-on a bounded sample of the same workload (few time steps).
+its average launch duration, timed with start/stop HIP events attached to
+sampled dispatches on the launch stream in one evaluation launched kernel by
+kernel right after the timed (graph-replayed) ones; ``traffic`` is the measured
+HBM bytes per launch (rocprofv3 counters, stored with a digest of the kernel
+sources) over the same duration.  ``cpu_baseline`` times the float64 oracle on
+this host's cores on a bounded sample of the same workload (100 time samples).
 """
 from __future__ import annotations
 
@@ -61,6 +64,7 @@ def pass_bytes(K: int) -> dict:
 
 
 PASS_BYTES = pass_bytes(8)
+STEP_BYTES = sum(PASS_BYTES.values())   # per grid point and time step, forward + adjoint
 
 # Measured HBM bytes per launch of the pass kinds (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by what the same counters read for a plain copy of known
@@ -91,7 +95,6 @@ def measured_traffic(kind: str, wl_name: str):
     if not e:
         return None
     return e["fetch_kib"] * 1024.0 * t["fetch_scale"] + e["write_kib"] * 1024.0 * t["write_scale"]
-STEP_BYTES = sum(PASS_BYTES.values())   # per grid point and time step, forward + adjoint
 
 
 def cpu_cores() -> int:
@@ -252,7 +255,7 @@ def main() -> int:
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint interval (0 = store the whole history)")
     ap.add_argument("--trace-every", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the checkpointed, batch and time-to-solution measurements")
     ap.add_argument("--batch-evals", type=int, default=5)

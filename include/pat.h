@@ -186,9 +186,10 @@ int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams
 #define PAT_PASS_ADJ_ROW_U    7
 #define PAT_PASS_KINDS        8
 /* pat_trace_start(every): from now on every `every`-th launch of each pass
- * kind is bracketed by two HIP events recorded on the stream it is launched
- * on (at most 1024 launches per kind; the events are created here, on the
- * current device).  pat_trace_stop() stops recording.  pat_trace_read(kind,
+ * kind carries two HIP events as the start and stop events of its own
+ * dispatch on the stream it is launched on, so their elapsed time is the
+ * kernel's execution (at most 1024 launches per kind; the events are created
+ * here, on the current device).  pat_trace_stop() stops recording.  pat_trace_read(kind,
  * &count, &total_ms): once those streams have drained, the number of timed
  * launches of `kind` and their summed duration in milliseconds.  Process-wide
  * state: not for concurrent use from several threads. */
