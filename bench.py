@@ -108,10 +108,11 @@ def cpu_cores() -> int:
     return max(1, min(n, 16))
 
 
-def cpu_baseline(nt_sample: int, K: int) -> dict:
-    """The float64 oracle, as it stands, on the W1 grid for nt_sample time samples."""
+def cpu_baseline(nt_sample: int, K: int, cores: int = 0) -> dict:
+    """The float64 oracle, as it stands, on the W1 grid for nt_sample time samples
+    (on ``cores`` threads; 0 = all this process may use, at most 16)."""
     from oracle import kspace
-    cores = cpu_cores()
+    cores = cores or cpu_cores()
     kspace.WORKERS = cores
     wl = I.w1(K=K, nt=nt_sample)
     c, p0 = I.phantoms(wl, 3)
@@ -125,6 +126,43 @@ def cpu_baseline(nt_sample: int, K: int) -> dict:
     return {"value": pts / dt, "unit": "grid-pt-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"float64 oracle (numpy + scipy.fft, {cores} threads), forward + adjoint on the "
                       f"512x512 grid, K={K}, {nt_sample} time samples ({dt:.1f} s)"}
+
+
+def forward_only(plan, wl, c, p0, data, ws, reps=2):
+    """Rate of the K forward solves alone (store-all recording, as in an evaluation)."""
+    import torch
+    g = wl.grid
+    plan.forward(c, p0, data, ws, record=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        plan.forward(c, p0, data, ws, record=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    return {"value": wl.K * g.nx * g.ny * g.nt / dt, "unit": "grid-pt-steps/s", "ms": round(1000.0 * dt, 2)}
+
+
+def bandwidth_probe():
+    """Achievable memory bandwidth on this GPU for context: device copies and
+    fills of buffers that fit the Infinity Cache (64 MB) and that do not (2 GB)."""
+    import torch
+    out = {}
+    for mb in (64, 2048):
+        n = mb * (1 << 20) // 4
+        x = torch.ones(n, device="cuda")
+        y = torch.empty_like(x)
+        for name, fn, nbytes in (("copy", lambda: y.copy_(x), 2 * 4 * n), ("fill", lambda: y.fill_(1.5), 4 * n)):
+            fn()
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            for _ in range(20):
+                fn()
+            e.record()
+            torch.cuda.synchronize()
+            out[f"{name}_{mb}MB_GBps"] = round(nbytes * 20 / (s.elapsed_time(e) / 1000.0) / 1e9, 1)
+        del x, y
+        torch.cuda.empty_cache()
+    return out
 
 
 def checkpointed(plan, wl, c, p0, y, w, evaluation_ms, s=64):
@@ -253,6 +291,8 @@ def main() -> int:
     ap.add_argument("--nt", type=int, default=4000)
     ap.add_argument("--K", type=int, default=8)
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint interval (0 = store the whole history)")
+    ap.add_argument("--tile", default="auto", choices=("auto", "0", "8"),
+                    help="column-pass tile width (auto: the autotuner's choice)")
     ap.add_argument("--trace-every", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=100)
@@ -280,6 +320,12 @@ def main() -> int:
     g = wl.grid
     c_true, p0 = I.phantoms(wl, 3)
     plan = pat.Plan(g, wl.K, wl.sensors)
+    if args.tile == "auto":
+        from paper_2505_08482_amd import tune
+        tile = tune.tile_for(g.nx, wl.K)     # measured once per GPU type and cached
+    else:
+        tile = int(args.tile)
+    plan.set_tile(tile)
     t_c_true = torch.from_numpy(c_true.astype(np.float32)).to(dev)
     t_p0 = torch.from_numpy(p0.astype(np.float32)).to(dev)
     ws = plan.workspace(args.ckpt)
@@ -352,6 +398,7 @@ def main() -> int:
         "config": {"workload": wl.name, "grid": f"{g.nx}x{g.ny}", "K": wl.K, "nt": g.nt, "sensors": wl.m,
                    "dx_m": g.dx, "dt_s": g.dt, "pml": g.pml,
                    "history": "store-all" if args.ckpt == 0 else f"checkpoint every {args.ckpt}",
+                   "column_tile": tile or "default",
                    "step": "recorded forward + misfit + adjoint gradient (g_p0 for all K, g_c)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -368,7 +415,9 @@ def main() -> int:
         "J": float(J.item()),
     }
     if not args.no_extras:
-        for name, fn in (("checkpointed", lambda: checkpointed(plan, wl, c, t_p0, y, w, evaluation_ms=ms)),
+        for name, fn in (("forward_only", lambda: forward_only(plan, wl, c, t_p0, data, ws)),
+                         ("bandwidth_probe", bandwidth_probe),
+                         ("checkpointed", lambda: checkpointed(plan, wl, c, t_p0, y, w, evaluation_ms=ms)),
                          ("batch", lambda: batch_w3(args.batch_evals)),
                          ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters))):
             try:
@@ -377,6 +426,8 @@ def main() -> int:
                 out[name] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, wl.K)
+        if not args.no_extras:
+            out["cpu_baseline_single_core"] = cpu_baseline(max(2, args.cpu_steps // 4), wl.K, cores=1)
     print(json.dumps(out), flush=True)
     plan.close()
     return 0

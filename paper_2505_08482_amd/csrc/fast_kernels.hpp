@@ -18,6 +18,7 @@
 //    column passes load 8..64 adjacent columns per block so that every load
 //    instruction touches contiguous 64-256 byte row segments.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -36,6 +37,13 @@ template <> struct Cfg<256> { static constexpr int T = 32; using L = RList<8, 8,
 template <> struct Cfg<128> { static constexpr int T = 16; using L = RList<8, 4, 4>; static constexpr int TC = 4; };
 template <> struct Cfg<64>  { static constexpr int T = 8;  using L = RList<8, 8>;    static constexpr int TC = 8; };
 template <> struct Cfg<32>  { static constexpr int T = 4;  using L = RList<8, 4>;    static constexpr int TC = 16; };
+
+// Element at a 32-bit byte offset from a (block-uniform) base: lets the
+// compiler address global memory as scalar base + 32-bit lane offset.
+template <class T>
+__device__ __forceinline__ T* at_byte(T* base, unsigned byte_off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
 
 // LDS position of element i: one pad slot per 8 keeps the radix-8 exchanges
 // (stride-8 writes, stride-1 reads) free of bank conflicts within a transform.
@@ -155,14 +163,14 @@ template <int N> using Fft = RegFft<N, typename Cfg<N>::L>;
 template <int N, int M>
 __device__ __forceinline__ float2 pack_folded(const float2* __restrict__ A, const float2* __restrict__ B, int q) {
   constexpr int T = N / 8;
-  const int k = q + T * M;
+  const unsigned k = q + T * M;
   if constexpr (M < 4) {
     const float2 a = A[k], b = B[k];
     const float2 gen = make_float2(a.x - b.y, a.y + b.x);
     if constexpr (M == 0) return q == 0 ? make_float2(a.x, b.x) : gen;   // DC: real parts
     return gen;
   } else {
-    const int idx = (M == 4 && q == 0) ? 0 : N - k;
+    const unsigned idx = (M == 4 && q == 0) ? 0u : N - k;
     const float2 a = A[idx], b = B[idx];
     const float2 gen = make_float2(a.x + b.y, b.x - a.y);                 // conj(a) + i conj(b)
     if constexpr (M == 4) return q == 0 ? make_float2(a.y, b.y) : gen;   // Nyquist, folded into bin 0
@@ -190,7 +198,7 @@ __device__ __forceinline__ void unpack_store(const float2 (&v)[8], int q, int la
     const float px = __shfl(v[7 - m].x, src);
     const float py = __shfl(v[7 - m].y, src);
     const float2 part = q == 0 ? v[(8 - m) & 7] : make_float2(px, py);
-    const int k = q + T * m;
+    const unsigned k = q + T * m;
     const float2 P = v[m], Q = make_float2(part.x, -part.y);   // Z[k], conj Z[N-k]
     float2 A = make_float2(0.5f * (P.x + Q.x), 0.5f * (P.y + Q.y));
     float2 B = make_float2(0.5f * (P.y - Q.y), -0.5f * (P.x - Q.x));
@@ -219,7 +227,8 @@ template <int N> struct RowF {
   constexpr int T = RC::T;                                                     \
   const int K = tb.K, ny = tb.ny, nhf = N / 2;                                 \
   const int k = blockIdx.x % K, ybase = (blockIdx.x / K) * RC::ROWS;           \
-  const int tid = threadIdx.x, grp = tid / T, q = tid % T, lane_base = grp * T; \
+  const int tid = threadIdx.x, q = tid % T;                                    \
+  const int grp = RC::G == 1 ? 0 : tid / T, lane_base = grp * T; /* uniform at G = 1 */ \
   const int y0 = ybase + 2 * grp, y1 = y0 + 1;                                 \
   (void)nhf;                                                                   \
   Fft<N> fft;                                                                  \
@@ -237,7 +246,7 @@ __global__ __launch_bounds__(64) void k_fwd_init(Tables tb, const float* __restr
   float2 v[1][8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const int x = q + T * m;
+    const unsigned x = q + T * m;
     float a = 0.f, b = 0.f;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -277,49 +286,60 @@ __global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux,
   float2 v[2][8];
   float ox[2][8], oy[2][8];
   const bool ok = y1 < ny;
+  // row pointers (block-uniform at one group per block) + unsigned lane offsets
+  float* uxr[2];
+  float* uyr[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
-    const float2* A = SA + ((size_t)k * ny + y) * nhf;
-    const float2* B = SB + ((size_t)k * ny + y) * nhf;
     const size_t f = ((size_t)k * ny + y) * N;
-    pack_row<N>(v[h], A, B, q);
+    uxr[h] = ux + f;
+    uyr[h] = uy + f;
+    pack_row<N>(v[h], SA + ((size_t)k * ny + y) * nhf, SB + ((size_t)k * ny + y) * nhf, q);
+    if (!first) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      if (!first) {
-        ox[h][m] = ux[f + q + T * m];
-        oy[h][m] = uy[f + q + T * m];
+      for (int m = 0; m < 8; ++m) {
+        ox[h][m] = uxr[h][(unsigned)(q + T * m)];
+        oy[h][m] = uyr[h][(unsigned)(q + T * m)];
       }
     }
   }
   // PML factors (prefetched before the transforms)
   float pax[8], pay[2];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) pax[m] = tb.asx[q + T * m];
+  for (int m = 0; m < 8; ++m) pax[m] = tb.asx[(unsigned)(q + T * m)];
   pay[0] = tb.asy[ok ? y0 : 0];
   pay[1] = tb.asy[ok ? y1 : 0];
   float2* L[2] = {X[grp][0], X[grp][1]};
   fft.template run<+1, 2>(v, L, q);
+  // step 0 starts from u^{-1/2} = G/2 (a uniform branch, not a per-element select)
+  auto update = [&](auto first_c) {
+    constexpr bool F0 = decltype(first_c)::value;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int y = ok ? y0 + h : 0;
-    const float ays = pay[h];
-    const size_t f = ((size_t)k * ny + y) * N;
+    for (int h = 0; h < 2; ++h) {
+      const float ays = pay[h];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int x = q + T * m;
-      const float2 g = v[h][m];
-      const float axs = pax[m];
-      const float uxo = first ? 0.5f * g.x : ox[h][m];
-      const float uyo = first ? 0.5f * g.y : oy[h][m];
-      const float nux = axs * (axs * uxo - g.x);
-      const float nuy = ays * (ays * uyo - g.y);
-      if (ok) {
-        ux[f + x] = nux;
-        uy[f + x] = nuy;
+      for (int m = 0; m < 8; ++m) {
+        const float2 g = v[h][m];
+        const float axs = pax[m];
+        const float uxo = F0 ? 0.5f * g.x : ox[h][m];
+        const float uyo = F0 ? 0.5f * g.y : oy[h][m];
+        v[h][m] = make_float2(axs * (axs * uxo - g.x), ays * (ays * uyo - g.y));
       }
-      v[h][m] = make_float2(nux, nuy);
     }
+  };
+  if (first)
+    update(std::true_type{});
+  else
+    update(std::false_type{});
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        uxr[h][(unsigned)(q + T * m)] = v[h][m].x;
+        uyr[h][(unsigned)(q + T * m)] = v[h][m].y;
+      }
   }
   fft.template run<-1, 2>(v, L, q);
   if (ok) {
@@ -346,24 +366,30 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
   float2 v[2][8];
   float orx[2][8], ory[2][8], cc[2][8];
   const bool ok = y1 < ny;
+  // row pointers (block-uniform at one group per block) + unsigned lane offsets
+  float* rxr[2];
+  float* ryr[2];
+  float* hr[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
-    const float2* A = SA + ((size_t)k * ny + y) * nhf;
-    const float2* B = SB + ((size_t)k * ny + y) * nhf;
     const size_t f = ((size_t)k * ny + y) * N;
-    pack_row<N>(v[h], A, B, q);
+    rxr[h] = rx + f;
+    ryr[h] = ry + f;
+    hr[h] = hist ? hist + f : nullptr;
+    const float* cr = c + (size_t)y * N;
+    pack_row<N>(v[h], SA + ((size_t)k * ny + y) * nhf, SB + ((size_t)k * ny + y) * nhf, q);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int x = q + T * m;
-      orx[h][m] = rx[f + x];
-      ory[h][m] = ry[f + x];
-      cc[h][m] = c[(size_t)y * N + x];
+      const unsigned x = q + T * m;
+      orx[h][m] = rxr[h][x];
+      ory[h][m] = ryr[h][x];
+      cc[h][m] = cr[x];
     }
   }
   float pax[8], pay[2];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) pax[m] = tb.ax[q + T * m];
+  for (int m = 0; m < 8; ++m) pax[m] = tb.ax[(unsigned)(q + T * m)];
   pay[0] = tb.ay[ok ? y0 : 0];
   pay[1] = tb.ay[ok ? y1 : 0];
   // sensor taps of this block's rows (one entry per thread, prefetched)
@@ -376,25 +402,41 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
   float2 z[1][8];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int y = ok ? y0 + h : 0;
     const float ays = pay[h];
-    const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int x = q + T * m;
       const float2 d = v[h][m];
       const float axs = pax[m];
       const float nrx = axs * (axs * orx[h][m] - d.x);
       const float nry = ays * (ays * ory[h][m] - d.y);
+      orx[h][m] = nrx;
+      ory[h][m] = nry;
       const float p = (cc[h][m] * cc[h][m]) * (nrx + nry);
-      if (ok) {
-        rx[f + x] = nrx;
-        ry[f + x] = nry;
-        if (hist) hist[f + x] = p;
-      }
-      P[2 * grp + h][x] = ok ? p : 0.f;
       if (h == 0) z[0][m].x = p; else z[0][m].y = p;
     }
+  }
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const unsigned x = q + T * m;
+        const float p = h == 0 ? z[0][m].x : z[0][m].y;
+        rxr[h][x] = orx[h][m];
+        ryr[h][x] = ory[h][m];
+        P[2 * grp + h][x] = p;
+      }
+    if (hist) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) hr[h][(unsigned)(q + T * m)] = h == 0 ? z[0][m].x : z[0][m].y;
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) P[2 * grp + h][q + T * m] = 0.f;
   }
   __syncthreads();
   if (dpart_n) {
@@ -435,12 +477,12 @@ struct AdjBlk {
     G = (tb.K + KB - 1) / KB;
     kg = blockIdx.x % G;
     ybase = (blockIdx.x / G) * RC::ROWS;
-    wave = threadIdx.x / 64;
+    wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);   // wave-uniform: scalar row addresses
     lane = threadIdx.x % 64;
     kw = kg * KB + wave;
     act = kw < tb.K;
     k = act ? kw : tb.K - 1;
-    grp = lane / T;
+    grp = RC::G == 1 ? 0 : lane / T;   // a literal 0 keeps the row index uniform
     q = lane % T;
     lane_base = grp * T;
     y0 = ybase + 2 * grp;
@@ -501,25 +543,32 @@ __global__ __launch_bounds__(64 * KB) void k_adj_rho(Tables tb, const float* __r
     const float2* B = SA + ((size_t)k * ny + (ok ? y0 + 1 : 0)) * nhf;
     pack_row<N>(v[0], A, B, q);
   }
+  // row pointers (block-uniform at one group per block) + unsigned lane offsets
+  float* rxr[2];
+  float* ryr[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
     const size_t f = ((size_t)k * ny + y) * N;
+    rxr[h] = rhx + f;
+    ryr[h] = rhy + f;
+    const float* pr = p_n + f;
+    const float* cr = c + (size_t)y * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int x = q + T * m;
-      orx[h][m] = rhx[f + x];
-      ory[h][m] = rhy[f + x];
-      op[h][m] = p_n[f + x];
-      oc[h][m] = c[(size_t)y * N + x];
+      const unsigned x = q + T * m;
+      orx[h][m] = rxr[h][x];
+      ory[h][m] = ryr[h][x];
+      op[h][m] = pr[x];
+      oc[h][m] = cr[x];
     }
   }
   b.load_slice(tb, gcg, gp);
   float pax[8], pax2[8], pay[2], pay2[2];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    pax[m] = tb.ax[q + T * m];
-    pax2[m] = tb.ax2[q + T * m];
+    pax[m] = tb.ax[(unsigned)(q + T * m)];
+    pax2[m] = tb.ax2[(unsigned)(q + T * m)];
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -569,12 +618,10 @@ __global__ __launch_bounds__(64 * KB) void k_adj_rho(Tables tb, const float* __r
   float2 w[2][8];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int y = ok ? y0 + h : 0;
     const float ays = pay[h], ay2s = pay2[h];
-    const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int x = q + T * m;
+      const unsigned x = q + T * m;
       const float ph = P[2 * grp + h][x];
       const float cv = oc[h][m];
       const float c2 = cv * cv;
@@ -583,12 +630,19 @@ __global__ __launch_bounds__(64 * KB) void k_adj_rho(Tables tb, const float* __r
       // this dataset's sound-speed term, 2/c with the hardware reciprocal (1 ulp);
       // left in place of ph (each lane rereads only its own pixels)
       P[2 * grp + h][x] = (2.0f * __builtin_amdgcn_rcpf(cv)) * op[h][m] * ph;
-      if (st) {
-        rhx[f + x] = pax2[m] * nrx;
-        rhy[f + x] = ay2s * nry;
-      }
+      orx[h][m] = pax2[m] * nrx;
+      ory[h][m] = ay2s * nry;
       w[h][m] = make_float2(pax[m] * nrx, ays * nry);
     }
+  }
+  if (st) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        rxr[h][(unsigned)(q + T * m)] = orx[h][m];
+        ryr[h][(unsigned)(q + T * m)] = ory[h][m];
+      }
   }
   __syncthreads();
   b.reduce_store(tb, PH, gp, gcg);
@@ -615,17 +669,20 @@ __global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx
   float2 v[2][8];
   float ox[2][8], oy[2][8];
   const bool ok = y1 < ny;
+  // row pointers (block-uniform at one group per block) + unsigned lane offsets
+  float* uxr[2];
+  float* uyr[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int y = ok ? y0 + h : 0;
-    const float2* A = SA + ((size_t)k * ny + y) * nhf;
-    const float2* B = SB + ((size_t)k * ny + y) * nhf;
     const size_t f = ((size_t)k * ny + y) * N;
-    pack_row<N>(v[h], A, B, q);
+    uxr[h] = uhx + f;
+    uyr[h] = uhy + f;
+    pack_row<N>(v[h], SA + ((size_t)k * ny + y) * nhf, SB + ((size_t)k * ny + y) * nhf, q);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      ox[h][m] = uhx[f + q + T * m];
-      oy[h][m] = uhy[f + q + T * m];
+      ox[h][m] = uxr[h][(unsigned)(q + T * m)];
+      oy[h][m] = uyr[h][(unsigned)(q + T * m)];
     }
   }
   const float* wxt = final_ ? tb.wfx : tb.asx;
@@ -633,8 +690,8 @@ __global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx
   float pa2x[8], pwx[8], pa2y[2], pwy[2];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    pa2x[m] = tb.asx2[q + T * m];
-    pwx[m] = wxt[q + T * m];
+    pa2x[m] = tb.asx2[(unsigned)(q + T * m)];
+    pwx[m] = wxt[(unsigned)(q + T * m)];
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -645,22 +702,23 @@ __global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx
   fft.template run<+1, 2>(v, L, q);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int y = ok ? y0 + h : 0;
     const float a2y = pa2y[h];
-    const float wy = pwy[h];
-    const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int x = q + T * m;
       const float2 g = v[h][m];
-      const float nux = pa2x[m] * ox[h][m] + g.x;
-      const float nuy = a2y * oy[h][m] + g.y;
-      if (ok) {
-        uhx[f + x] = nux;
-        uhy[f + x] = nuy;
-      }
-      v[h][m] = make_float2(pwx[m] * nux, wy * nuy);
+      ox[h][m] = pa2x[m] * ox[h][m] + g.x;
+      oy[h][m] = a2y * oy[h][m] + g.y;
+      v[h][m] = make_float2(pwx[m] * ox[h][m], pwy[h] * oy[h][m]);
     }
+  }
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        uxr[h][(unsigned)(q + T * m)] = ox[h][m];
+        uyr[h][(unsigned)(q + T * m)] = oy[h][m];
+      }
   }
   fft.template run<-1, 2>(v, L, q);
   if (ok) {
@@ -714,7 +772,7 @@ __global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* _
     const size_t f = ((size_t)k * ny + y) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int x = q + T * m;
+      const unsigned x = q + T * m;
       const float cv = c[(size_t)y * N + x];
       const float rs = rhx[f + x] + rhy[f + x];
       if (ok && b.act) gp0[f + x] = P[2 * grp + h][x] + rs * (0.5f / (cv * cv));
@@ -745,15 +803,18 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
   const int k = blockIdx.x % K, c0 = (blockIdx.x / K) * TC;
   const int tid = threadIdx.x, cl = tid % TC, q = tid / TC, cx = c0 + cl;
   const bool ok = cx < nhf;
-  const size_t base = (size_t)k * N * nhf;
+  // dataset base pointers (block-uniform) + 32-bit byte offsets per lane and row
+  float2* const colA = SA + (size_t)k * N * nhf;
+  float2* const colB = SB + (size_t)k * N * nhf;
+  const unsigned lane_b = ((unsigned)q * nhf + (ok ? cx : 0)) * 8u, row_b = (unsigned)T * nhf * 8u;
   Fft<N> fft;
   fft.init(tb.tw_y, q);
   float2 a[2][8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const size_t i = base + (size_t)(q + T * m) * nhf + (ok ? cx : 0);
-    a[0][m] = SA[i];
-    if (TWO_IN) a[1][m] = SB[i];
+    const unsigned o = lane_b + m * row_b;
+    a[0][m] = *at_byte(colA, o);
+    if (TWO_IN) a[1][m] = *at_byte(colB, o);
   }
   // spectral multiplier factors (prefetched before the transforms)
   constexpr bool PLUS = MODE == COL_GRAD1 || MODE == COL_PAIRP;
@@ -843,9 +904,9 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
   if (ok) {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const size_t i = base + (size_t)(q + T * m) * nhf + cx;
-      SA[i] = a[0][m];
-      if (TWO_OUT) SB[i] = a[1][m];
+      const unsigned o = lane_b + m * row_b;
+      *at_byte(colA, o) = a[0][m];
+      if (TWO_OUT) *at_byte(colB, o) = a[1][m];
     }
   }
 }
