@@ -7,6 +7,13 @@ import numpy as np
 from oracle import kspace
 from paper_2505_08482_amd import inputs as I
 
+# the oracle's FFTs use this process's CPU share (at most 16 threads)
+try:
+    import os as _os
+    kspace.WORKERS = max(1, min(16, len(_os.sched_getaffinity(0))))
+except (AttributeError, OSError):
+    kspace.WORKERS = 1
+
 
 def announce(msg: str) -> None:
     print(f"\n[gpu-case] {msg}", flush=True)

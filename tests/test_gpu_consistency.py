@@ -68,15 +68,15 @@ def test_batch_equals_single_runs_bitwise(K):
 
 
 def test_oracle_parity_512_short():
-    wl = I.w1(K=1, nt=150)
+    wl = I.w1(K=1, nt=400)
     c_true, p0 = I.phantoms(wl, 3)
     c_true = c_true.astype(np.float32)
     p0 = p0.astype(np.float32)
     y, w = observed_data(wl, c_true, p0, noise_seed=3500)
     c = np.full_like(c_true, np.float32(1500.0))
-    announce("512 K=1 nt=150 oracle")
+    announce("512 K=1 nt=400 oracle")
     ora = oracle_forward_adjoint(wl, c, p0, y=y, w=w)
-    announce("512 K=1 nt=150 gpu")
+    announce("512 K=1 nt=400 gpu")
     gpu = gpu_forward_adjoint(wl, c, p0, resid32=ora["resid"].astype(np.float32))
     e = (rel_l2(gpu["data"], ora["data"]), rel_l2(gpu["g_p0"], ora["g_p0"]), rel_l2(gpu["g_c"], ora["g_c"]))
     print(f"[parity] 512 short: {e}", flush=True)

@@ -51,12 +51,18 @@ def test_config1_full_84x84_k1_600_steps():
     _parity(I.config1(), 1)
 
 
-def test_config2_256x256_k2_reduced_steps():
-    _parity(_reduced(I.config2(), nt=240, K=2, name="cfg2_256_K2_nt240"), 2)
+def test_config2_full_256x256_k4_2000_steps():
+    _parity(I.config2(), 2)
 
 
-def test_config3_level128_k8():
-    _parity(_reduced(I.config3_level(128), nt=250, name="cfg3_128_K8_nt250"), 3)
+def test_config3_level128_full_k8_1000_steps():
+    _parity(I.config3_level(128), 3)
+
+
+def test_config3_level256_k8_500_steps():
+    """The 256^2 multigrid level with all 8 datasets on a quarter of its time
+    axis (the float64 oracle needs about a minute per 1e9 grid-point steps)."""
+    _parity(_reduced(I.config3_level(256), nt=500, name="cfg3_256_K8_nt500"), 3)
 
 
 def test_radix3_192_k2():
