@@ -165,6 +165,49 @@ def bandwidth_probe():
     return out
 
 
+def paper_geometry(iters: int = 40, levels=("mg1", "mg2", "mg3", "mg4")):
+    """The paper's own set-up (Sec. 4, Table 1): 236 sensors on the square around
+    the 20 mm target, the nine-disc stand-in phantom with four initial pressures,
+    data simulated on the 375^2 data grid (not a reconstruction grid) with 1 %
+    noise, and multigrid reconstructions over Table 1's grids 1-4 with all four
+    datasets (K = 4) and with the first alone (K = 1, the paper's reference
+    approach); c in [1300, 1800] m/s, starting at 1505 m/s, 1430 m/s held
+    outside the target square.  E_c and E_p0 of dataset 1 on the finest level."""
+    import torch
+    from paper_2505_08482_amd import pat, recon
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    wd = I.paper_level("data", K=4)
+    cd, p0d = I.nine_disc_phantom(wd.grid, 4)
+    plan = pat.Plan(wd.grid, 4, wd.sensors)
+    ws = plan.workspace(0)
+    data = torch.empty(plan.data_shape, device="cuda")
+    t = time.perf_counter()
+    plan.forward(T(cd), T(p0d), data, ws, record=False)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t
+    plan.close()
+    del ws
+    noisy, sigma = I.add_noise(data.cpu().numpy().astype(np.float64), seed=6500)
+    out = {"data_grid": wd.grid.nx, "data_nt": wd.grid.nt, "data_seconds": round(t_data, 3),
+           "sensors": wd.m, "levels": [I.paper_grid(n).nx for n in levels], "iters_per_level": iters}
+    for K in (4, 1):
+        lv = [I.paper_level(n, K) for n in levels]
+        t = time.perf_counter()
+        res = recon.multigrid(lv, T(noisy[:K]), wd.grid.dt, T(1.0 / sigma[:K]),
+                              lambda wl: T(I.nine_disc_phantom(wl.grid, 1)[0]), c_lo=1300.0, c_hi=1800.0,
+                              iters=iters, c_init=1505.0, c_fixed=1430.0)
+        secs = time.perf_counter() - t
+        fine = lv[-1]
+        p0t = I.nine_disc_phantom(fine.grid, 1)[1][0]
+        m = fine.mask()
+        p0r = res["p0"][0].cpu().numpy().astype(np.float64)
+        e_p0 = 100.0 * float(np.linalg.norm((p0r - p0t)[m]) / np.linalg.norm(p0t[m]))
+        out[f"K{K}"] = {"E_c_percent": round(res["E_c"], 3), "E_p0_1_percent": round(e_p0, 2),
+                        "seconds": round(secs, 2), "iterations": [r.iters for r in res["levels"]],
+                        "evals": [r.evals for r in res["levels"]]}
+    return out
+
+
 def checkpointed(plan, wl, c, p0, y, w, evaluation_ms, s=64):
     """The same evaluation with checkpoints every s steps and segment recompute."""
     import torch
@@ -267,14 +310,14 @@ def time_to_solution(wl_fine, c_true, y_fine, w, iters: int, target: float = 2.0
     out = recon.multigrid(levels, y_fine, wl_fine.grid.dt, w, c_true, iters=iters, log=cb)
     total = time.perf_counter() - t0
     # the target is judged on the finest level (E_c of coarse levels is measured
-    # against the resampled truth and is only reported)
-    elapsed = sum(lv.seconds for lv in out["levels"][:-1])
+    # against the resampled truth and is only reported); the time is wall clock
+    # from the start of the run (level set-up, plans and data resampling included)
     fine = out["levels"][-1]
     its_before = sum(lv.iters for lv in out["levels"][:-1])
     for i, (e, tt) in enumerate(zip(fine.E_c, fine.t)):
         if e <= target:
             reached = {"level": fine.n, "iteration_at_level": i + 1, "iterations_total": its_before + i + 1,
-                       "seconds": round(elapsed + tt, 2)}
+                       "seconds": round(fine.t_start + tt, 2)}
             break
     return {"target_E_c_percent": target, "reached": reached or None, "final_E_c_percent": round(out["E_c"], 3),
             "total_seconds": round(total, 2),
@@ -419,7 +462,8 @@ def main() -> int:
                          ("bandwidth_probe", bandwidth_probe),
                          ("checkpointed", lambda: checkpointed(plan, wl, c, t_p0, y, w, evaluation_ms=ms)),
                          ("batch", lambda: batch_w3(args.batch_evals)),
-                         ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters))):
+                         ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters)),
+                         ("paper_geometry", lambda: paper_geometry(args.tts_iters))):
             try:
                 out[name] = fn()
             except Exception as e:   # an extra must never cost the main line

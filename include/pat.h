@@ -118,6 +118,16 @@ int pat_project_update(int64_t n, float* x, const float* d, float alpha,
 int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc,
                 float* fine, int32_t nyf, int32_t nxf, void* stream);
 
+/* Sec. 3.1 for levels of different physical extent (Table 1's grids carry PML
+ * layers of different widths): bilinear interpolation of nchan coarse fields
+ * [nchan][nyc][nxc] with pixel spacing dxc (metres) onto [nchan][nyf][nxf]
+ * with spacing dxf, both grids centred on the origin (pixel i at
+ * (i + 1/2 - n/2) * dx), each fine value taken at its own physical position
+ * and clamped to the coarse grid.  Equals pat_prolong when nxc * dxc ==
+ * nxf * dxf.  PAT_EINVAL for null arrays, non-positive sizes or spacings. */
+int pat_prolong_phys(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, double dxc,
+                     float* fine, int32_t nyf, int32_t nxf, double dxf, void* stream);
+
 /* Sec. 4.1.2: linear interpolation in time of traces y [nlead][nt_src][m]
  * sampled at n*dt_src onto out [nlead][nt_dst][m] at n*dt_dst (held at the
  * last sample beyond the end). */

@@ -12,7 +12,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
                          Sec. 3 (the pin for ``lbfgs_direction``).
 * ``projected_lbfgs``    eq. (10) iterations with a backtracking (Armijo) line
                          search, memory ``l`` (Sec. 4.1.2 uses l = 20).
-* ``prolong``            Sec. 3.1: linear (bilinear) interpolation of a converged
+* ``prolong``, ``prolong_phys``  Sec. 3.1: linear (bilinear) interpolation of a converged
                          coarse-grid solution to the next, finer grid.
 * ``time_interp``        Sec. 4.1.2: linear interpolation of the data onto a
                          level's time grid.
@@ -110,6 +110,26 @@ def prolong(coarse: np.ndarray, nyf: int, nxf: int) -> np.ndarray:
         t = f - i0
         i1 = np.minimum(i0 + 1, nc - 1)
         return i0, i1, t
+
+    iy0, iy1, ty = axis_weights(nyf, nyc)
+    ix0, ix1, tx = axis_weights(nxf, nxc)
+    rows = coarse[..., iy0, :] * (1.0 - ty)[:, None] + coarse[..., iy1, :] * ty[:, None]
+    return rows[..., :, ix0] * (1.0 - tx) + rows[..., :, ix1] * tx
+
+
+def prolong_phys(coarse: np.ndarray, dx_coarse: float, nyf: int, nxf: int, dx_fine: float) -> np.ndarray:
+    """Sec. 3.1 between grids of different physical extent, both centred on the
+    origin: each fine pixel (at ``(i + 1/2 - n/2) dx_fine``) takes the bilinear
+    interpolant of ``coarse [..., nyc, nxc]`` (spacing ``dx_coarse``) at its own
+    position, clamped to the coarse grid."""
+    coarse = np.asarray(coarse, dtype=np.float64)
+    nyc, nxc = coarse.shape[-2:]
+
+    def axis_weights(nf, nc):
+        x = (np.arange(nf) + 0.5 - nf / 2.0) * dx_fine          # physical position
+        f = np.clip(x / dx_coarse + nc / 2.0 - 0.5, 0.0, nc - 1.0)  # fractional coarse index
+        i0 = np.minimum(np.floor(f).astype(np.int64), max(nc - 2, 0))
+        return i0, np.minimum(i0 + 1, nc - 1), f - i0
 
     iy0, iy1, ty = axis_weights(nyf, nyc)
     ix0, ix1, tx = axis_weights(nxf, nxc)

@@ -996,6 +996,17 @@ int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, fl
   return last_error();
 }
 
+int pat_prolong_phys(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, double dxc, float* fine,
+                     int32_t nyf, int32_t nxf, double dxf, void* stream) {
+  if (nchan <= 0 || nyc <= 0 || nxc <= 0 || nyf <= 0 || nxf <= 0 || !coarse || !fine || !(dxc > 0.0) ||
+      !(dxf > 0.0))
+    return PAT_EINVAL;
+  const int64_t n = (int64_t)nchan * nyf * nxf;
+  hipLaunchKernelGGL(k_prolong_phys, dim3(grid_blocks(n)), dim3(256), 0, static_cast<hipStream_t>(stream), nchan,
+                     coarse, nyc, nxc, dxc, fine, nyf, nxf, dxf);
+  return last_error();
+}
+
 int pat_time_interp(int32_t nlead, int32_t nt_src, int32_t m, const float* y, double dt_src, float* out,
                     int32_t nt_dst, double dt_dst, void* stream) {
   if (nlead <= 0 || nt_src <= 0 || m <= 0 || nt_dst <= 0 || !y || !out || !(dt_src > 0) || !(dt_dst > 0))

@@ -131,6 +131,39 @@ __global__ void k_prolong(int nchan, const float* __restrict__ coarse, int nyc, 
   }
 }
 
+// Bilinear at the same physical point: fine pixel i sits at (i + 1/2 - nf/2) dxf,
+// i.e. at the fractional coarse index x / dxc + nc/2 - 1/2 (both grids centred
+// on the origin); clamped to the coarse grid.
+__device__ __forceinline__ void axis_tap_phys(int i, int nf, double dxf, int nc, double dxc, int& i0, int& i1,
+                                              float& t) {
+  double f = ((i + 0.5 - 0.5 * nf) * dxf) / dxc + 0.5 * nc - 0.5;
+  f = f < 0.0 ? 0.0 : (f > nc - 1.0 ? nc - 1.0 : f);
+  int a = (int)floor(f);
+  const int amax = nc >= 2 ? nc - 2 : 0;
+  a = a > amax ? amax : a;
+  i0 = a;
+  i1 = a + 1 < nc ? a + 1 : nc - 1;
+  t = (float)(f - a);
+}
+
+__global__ void k_prolong_phys(int nchan, const float* __restrict__ coarse, int nyc, int nxc, double dxc,
+                               float* __restrict__ fine, int nyf, int nxf, double dxf) {
+  const int64_t n = (int64_t)nchan * nyf * nxf;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nxf);
+    const int y = (int)((i / nxf) % nyf);
+    const int64_t ch = i / ((int64_t)nxf * nyf);
+    int x0, x1, y0, y1;
+    float tx, ty;
+    axis_tap_phys(x, nxf, dxf, nxc, dxc, x0, x1, tx);
+    axis_tap_phys(y, nyf, dxf, nyc, dxc, y0, y1, ty);
+    const float* cc = coarse + ch * (int64_t)nyc * nxc;
+    const float r0 = cc[(int64_t)y0 * nxc + x0] * (1.f - tx) + cc[(int64_t)y0 * nxc + x1] * tx;
+    const float r1 = cc[(int64_t)y1 * nxc + x0] * (1.f - tx) + cc[(int64_t)y1 * nxc + x1] * tx;
+    fine[i] = r0 * (1.f - ty) + r1 * ty;
+  }
+}
+
 __global__ void k_time_interp(int nlead, int nt_src, int m, const float* __restrict__ y, double dt_src,
                               float* __restrict__ out, int nt_dst, double dt_dst) {
   const int64_t n = (int64_t)nlead * nt_dst * m;

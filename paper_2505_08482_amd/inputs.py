@@ -80,10 +80,23 @@ class Workload:
     sensor_radius_px: float      # in pixels of this grid
     support_radius_px: float     # phantom support / reconstruction mask radius
     phys_px: Optional[int] = None  # side of the physical (non-PML) region if PML is outside
+    sensor_xy: Optional[np.ndarray] = None   # explicit sensor positions [m][2] (metres)
+    square_half: Optional[float] = None      # half side (metres) of a square reconstruction domain
 
     @property
     def sensors(self) -> np.ndarray:
+        if self.sensor_xy is not None:
+            return self.sensor_xy
         return circle_sensors(self.m, self.sensor_radius_px * self.grid.dx)
+
+    def mask(self) -> np.ndarray:
+        """Reconstruction domain ``[ny][nx]`` (bool): the square of half side
+        ``square_half`` if set, else the disc of radius ``support_radius_px``."""
+        g = self.grid
+        if self.square_half is not None:
+            X, Y = np.meshgrid(pixel_centres(g.nx) * g.dx, pixel_centres(g.ny) * g.dx)
+            return (np.abs(X) <= self.square_half) & (np.abs(Y) <= self.square_half)
+        return mask_disc(g.nx, self.support_radius_px)
 
 
 def sensor_radius_px(n: int) -> int:
@@ -129,6 +142,80 @@ def w1(K: int = 8, nt: int = 4000) -> Workload:
     wl = config3_level(512, K=K, nt=nt)
     wl.name = f"w1_512x512_K{K}_nt{nt}"
     return wl
+
+
+# ---------------------------------------------------------------------------
+# The paper's own geometry (Sec. 4, Table 1)
+# ---------------------------------------------------------------------------
+# Table 1 rows: pixel size dz (m), target pixels Nz, sensor-layer pixels NzS and
+# PML pixels NzPML.  The reconstruction grids add both layers on every side
+# (Nz + 2 NzS + 2 NzPML = 81, 125, 125, 175, 243); the data row's Nz = 335
+# already holds its two 10-pixel sensor layers, so its FFT grid is
+# 335 + 2 * 20 = 375.
+TABLE1 = {
+    "data": (63.7e-6, 335, 10, 20),
+    "mg1": (526.3e-6, 39, 2, 19),
+    "mg2": (370.4e-6, 55, 4, 31),
+    "mg3": (227.3e-6, 89, 4, 14),
+    "mg4": (156.3e-6, 129, 6, 17),
+    "mg5": (101.0e-6, 199, 8, 14),
+}
+PAPER_SIDE = 20e-3          # m, side of the square target domain (Sec. 4)
+PAPER_SENSOR_OFFSET = 0.2e-3  # m, distance of the sensors from the domain boundary
+PAPER_SENSORS = 236
+PAPER_DURATION = 21.15e-6   # s, the common time span Nt * dt of Table 1's grids
+
+
+def paper_grid(name: str) -> Grid:
+    """FFT grid of a Table 1 row; the time step follows this build's CFL rule
+    (c_ref = 1600 m/s) over the table's common duration."""
+    dz, nz, ns, npml = TABLE1[name]
+    n = nz + 2 * npml + (0 if name == "data" else 2 * ns)
+    dt = cfl_dt(dz)
+    return Grid(nx=n, ny=n, dx=dz, dt=dt, nt=int(round(PAPER_DURATION / dt)) + 1, pml=npml)
+
+
+def square_array(m: int = PAPER_SENSORS, side: float = PAPER_SIDE, offset: float = PAPER_SENSOR_OFFSET) -> np.ndarray:
+    """``m`` point sensors evenly spaced along the square of side
+    ``side + 2 offset`` centred on the origin (``m/4`` per side, the first half
+    a spacing from a corner): the planar detection geometry of Sec. 4."""
+    if m % 4:
+        raise ValueError("the square array needs a multiple of 4 sensors")
+    h = side / 2.0 + offset
+    per = m // 4
+    s = (np.arange(per, dtype=np.float64) + 0.5) * (2.0 * h / per) - h
+    sides = [np.stack([s, np.full(per, -h)], 1), np.stack([np.full(per, h), s], 1),
+             np.stack([-s, np.full(per, h)], 1), np.stack([np.full(per, -h), -s], 1)]
+    return np.concatenate(sides, axis=0)
+
+
+def paper_level(name: str, K: int) -> Workload:
+    """One Table 1 grid with the 236-sensor square array and the 20 mm target square."""
+    g = paper_grid(name)
+    return Workload(f"paper_{name}_{g.nx}_K{K}", g, K=K, m=PAPER_SENSORS, sensor_radius_px=0.0,
+                    support_radius_px=0.0, sensor_xy=square_array(), square_half=PAPER_SIDE / 2.0)
+
+
+def nine_disc_phantom(grid: Grid, K: int = 4, background: float = 1430.0, inclusion: float = 1580.0,
+                      p0_value: float = 10.0, seed: int = 6000) -> Tuple[np.ndarray, np.ndarray]:
+    """A synthetic stand-in of the simple phantom of Sec. 4.1.1: nine discs
+    (radius 1.5 mm, on a 3 x 3 lattice of pitch 6 mm) at ``inclusion`` in a
+    ``background`` medium, and K initial pressures, each three discs (radius
+    1 mm, ``p0_value`` Pa) at seeded positions inside the target square
+    (dataset k uses ``seed + k``).  The layout is this build's, drawn
+    analytically on ``grid`` (a pixel belongs to a disc if its centre does)."""
+    X, Y = np.meshgrid(pixel_centres(grid.nx) * grid.dx, pixel_centres(grid.ny) * grid.dx)
+    c = np.full((grid.ny, grid.nx), background)
+    for cx in (-6e-3, 0.0, 6e-3):
+        for cy in (-6e-3, 0.0, 6e-3):
+            c[(X - cx) ** 2 + (Y - cy) ** 2 <= (1.5e-3) ** 2] = inclusion
+    p0 = np.zeros((K, grid.ny, grid.nx))
+    for k in range(K):
+        rng = np.random.default_rng(seed + k + 1)
+        for _ in range(3):
+            cx, cy = rng.uniform(-8.5e-3, 8.5e-3, size=2)
+            p0[k][(X - cx) ** 2 + (Y - cy) ** 2 <= (1.0e-3) ** 2] = p0_value
+    return c, p0
 
 
 # ---------------------------------------------------------------------------

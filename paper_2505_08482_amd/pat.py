@@ -20,7 +20,7 @@ PAT_OK, PAT_EINVAL, PAT_EUNSUPPORTED, PAT_EWORKSPACE, PAT_EHIP = 0, -1, -2, -3, 
 
 EXPORTS = (
     "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_misfit",
-    "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_time_interp",
+    "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_prolong_phys", "pat_time_interp",
     "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_dot", "pat_status_string",
     "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_batch_gradient",
 )
@@ -70,6 +70,7 @@ def lib() -> ctypes.CDLL:
     L.pat_adjoint_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.pat_project_update.argtypes = [i64, vp, vp, f32, vp, vp, f32, f32, vp]
     L.pat_prolong.argtypes = [i32, vp, i32, i32, vp, i32, i32, vp]
+    L.pat_prolong_phys.argtypes = [i32, vp, i32, i32, ctypes.c_double, vp, i32, i32, ctypes.c_double, vp]
     L.pat_time_interp.argtypes = [i32, i32, i32, vp, f64, vp, i32, f64, vp]
     L.pat_lbfgs_scratch_bytes.argtypes = [i32]
     L.pat_lbfgs_scratch_bytes.restype = sz
@@ -215,6 +216,17 @@ def prolong(coarse, fine):
     if nchan != nchan2:
         raise ValueError("channel mismatch")
     _check(lib().pat_prolong(nchan, _f32(coarse), nyc, nxc, _f32(fine), nyf, nxf, _stream()), "pat_prolong")
+
+
+def prolong_phys(coarse, dx_coarse: float, fine, dx_fine: float):
+    """``coarse [nchan][nyc][nxc]`` (spacing ``dx_coarse``) -> ``fine [nchan][nyf][nxf]``
+    (spacing ``dx_fine``), both centred on the origin."""
+    nchan, nyc, nxc = coarse.shape
+    nchan2, nyf, nxf = fine.shape
+    if nchan != nchan2:
+        raise ValueError("channel mismatch")
+    _check(lib().pat_prolong_phys(nchan, _f32(coarse), nyc, nxc, float(dx_coarse), _f32(fine), nyf, nxf,
+                                  float(dx_fine), _stream()), "pat_prolong_phys")
 
 
 def time_interp(y, dt_src: float, out, dt_dst: float):

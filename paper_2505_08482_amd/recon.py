@@ -7,7 +7,8 @@
   (Alg. 1, memory l) and ``pat_project_update`` (eq. (11)), backtracking
   (Armijo) line search with trial forward solves only;
 * multigrid continuation (Sec. 3.1): coarse-to-fine levels, the converged
-  iterate carried to the next level with ``pat_prolong`` and the data
+  iterate carried to the next level with ``pat_prolong_phys`` (same physical
+  positions, levels of any extent) and the data
   resampled onto each level's time grid with ``pat_time_interp`` (Sec. 4.1.2).
 
 The optimiser works on scaled variables ``z = x / scale`` (per block: p0 and c).
@@ -37,6 +38,7 @@ class LevelResult:
     seconds: float
     E_c: List[float]
     t: List[float]          # seconds since the start of the level, per iteration
+    t_start: float = 0.0    # seconds from the start of the multigrid run to the start of the level
 
 
 class Problem:
@@ -54,7 +56,7 @@ class Problem:
         self.N = g.nx * g.ny
         self.K = wl.K
         self.n = (self.K + 1) * self.N
-        mask = torch.from_numpy(I.mask_disc(g.nx, wl.support_radius_px).astype(np.bool_)).to(device)
+        mask = torch.from_numpy(wl.mask().astype(np.bool_)).to(device)
         # bounds (eq. (11)): p0 >= 0, c in [c_lo, c_hi]; outside the mask both are pinned
         lo = torch.empty(self.n, dtype=torch.float32, device=device)
         hi = torch.empty_like(lo)
@@ -182,9 +184,15 @@ def relative_error_c(prob: Problem, z: torch.Tensor, c_true: torch.Tensor) -> fl
 
 def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w: torch.Tensor, c_true_fine,
               c_lo: float = 1400.0, c_hi: float = 1600.0, iters: int = 40, memory: int = 20,
-              ckpt_every: int = 0, target_Ec: Optional[float] = None, log: Optional[Callable] = None):
-    """Coarse-to-fine reconstruction (Sec. 3.1).  ``c_true_fine`` (torch, finest
-    grid) only measures E_c; it never enters the optimisation."""
+              ckpt_every: int = 0, target_Ec: Optional[float] = None, log: Optional[Callable] = None,
+              c_init: Optional[float] = None, c_fixed: float = 1500.0):
+    """Coarse-to-fine reconstruction (Sec. 3.1).  ``c_true_fine`` only measures
+    E_c and never enters the optimisation: a tensor on the finest grid
+    (resampled to coarser levels), or a callable ``level workload -> tensor``.
+    Levels may differ in physical extent (Table 1); the converged iterate is
+    carried to the next level at the same physical positions.  ``c_init``: the
+    starting sound speed inside the mask (default: the middle of the bounds);
+    ``c_fixed``: the sound speed held outside the mask."""
     device = y_fine.device
     results: List[LevelResult] = []
     z_prev = None
@@ -194,23 +202,28 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
         g = wl.grid
         y = torch.empty((wl.K, g.nt, wl.m), dtype=torch.float32, device=device)
         pat.time_interp(y_fine, dt_fine, y, g.dt)
-        prob = Problem(wl, y, w, c_lo, c_hi, ckpt_every=ckpt_every)
+        prob = Problem(wl, y, w, c_lo, c_hi, c_fixed=c_fixed, ckpt_every=ckpt_every)
         if z_prev is None:
             x0 = torch.empty(prob.n, dtype=torch.float32, device=device)
             x0[: prob.K * prob.N] = 0.0
-            x0[prob.K * prob.N:] = 0.5 * (c_lo + c_hi)
+            x0[prob.K * prob.N:] = 0.5 * (c_lo + c_hi) if c_init is None else c_init
         else:
-            xc = (z_prev * prev.scale).view(prev.K + 1, prev.wl.grid.ny, prev.wl.grid.nx).contiguous()
+            pg = prev.wl.grid
+            xc = (z_prev * prev.scale).view(prev.K + 1, pg.ny, pg.nx).contiguous()
             xf = torch.empty((prob.K + 1, g.ny, g.nx), dtype=torch.float32, device=device)
-            pat.prolong(xc, xf)
+            pat.prolong_phys(xc, pg.dx, xf, g.dx)
             x0 = xf.reshape(-1)
             prev.close()
         z0 = x0 / prob.scale
-        ct = c_true_fine
-        if ct.shape[-1] != g.nx:
-            ctf = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=device)
-            pat.prolong(c_true_fine.reshape(1, *c_true_fine.shape).contiguous(), ctf)
-            ct = ctf[0]
+        if callable(c_true_fine):
+            ct = c_true_fine(wl)
+        else:
+            ct = c_true_fine
+            if ct.shape[-1] != g.nx:
+                fg = levels[-1].grid
+                ctf = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=device)
+                pat.prolong_phys(c_true_fine.reshape(1, *c_true_fine.shape).contiguous(), fg.dx, ctf, g.dx)
+                ct = ctf[0]
         Ec = []
         Ts = []
         t0 = time.perf_counter()
@@ -223,11 +236,12 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
 
         z, J, hist, nit = projected_lbfgs(prob, z0, iters, memory=memory, callback=cb)
         torch.cuda.synchronize()
-        results.append(LevelResult(g.nx, nit, prob.evals, hist, time.perf_counter() - t0, Ec, Ts))
+        results.append(LevelResult(g.nx, nit, prob.evals, hist, time.perf_counter() - t0, Ec, Ts, t0 - t_all))
         z_prev, prev = z, prob
     x = z_prev * prev.scale
     p0, c = prev.split(x)
+    ct = c_true_fine(levels[-1]) if callable(c_true_fine) else c_true_fine
     out = {"levels": results, "p0": p0.clone(), "c": c.clone(), "seconds": time.perf_counter() - t_all,
-           "E_c": relative_error_c(prev, z_prev, c_true_fine)}
+           "E_c": relative_error_c(prev, z_prev, ct)}
     prev.close()
     return out

@@ -118,3 +118,23 @@ def test_single_time_sample_and_two_samples():
             assert np.all(gpu["g_c"] == 0.0)
         else:
             assert rel_l2(gpu["g_c"], gc) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("level", ["mg1", "mg4"])
+def test_paper_geometry_square_array_k4(level):
+    """Table 1 grids (81^2: radix 3; 175^2: radix 5 and 7) with the 236-sensor
+    square array and the nine-disc stand-in, K = 4, on a shortened time axis."""
+    wl0 = I.paper_level(level, K=4)
+    wl = dataclasses.replace(wl0, grid=dataclasses.replace(wl0.grid, nt=160), name=f"paper_{level}_K4_nt160")
+    c_true, p0 = I.nine_disc_phantom(wl.grid, 4)
+    c_true = c_true.astype(np.float32)
+    p0 = p0.astype(np.float32)
+    y, w = observed_data(wl, c_true, p0, noise_seed=6500)
+    c = np.full_like(c_true, np.float32(1505.0))
+    announce(f"{wl.name} oracle")
+    ora = oracle_forward_adjoint(wl, c, p0, y=y, w=w)
+    announce(f"{wl.name} gpu")
+    gpu = gpu_forward_adjoint(wl, c, p0, resid32=ora["resid"].astype(np.float32))
+    e = (rel_l2(gpu["data"], ora["data"]), rel_l2(gpu["g_p0"], ora["g_p0"]), rel_l2(gpu["g_c"], ora["g_c"]))
+    print(f"[parity] {wl.name}: {e}", flush=True)
+    assert e[0] <= DATA_TOL and e[1] <= GRAD_TOL and e[2] <= GRAD_TOL

@@ -71,6 +71,20 @@ def test_prolong(torch, shape):
     assert np.abs(fine.cpu().numpy() - ref).max() < 1e-3
 
 
+@pytest.mark.parametrize("levels", [("mg1", "mg2"), ("mg2", "mg3"), ("mg4", "mg5"), ("mg5", "mg1")])
+def test_prolong_phys_between_table1_grids(torch, levels):
+    """Levels of different physical extent (and, last, fine -> coarse)."""
+    from paper_2505_08482_amd import inputs as I, pat
+    gc, gf = I.paper_grid(levels[0]), I.paper_grid(levels[1])
+    rng = np.random.default_rng(5)
+    coarse = rng.uniform(1300, 1800, (2, gc.ny, gc.nx)).astype(np.float32)
+    announce(f"prolong_phys {levels}")
+    fine = torch.empty((2, gf.ny, gf.nx), dtype=torch.float32, device="cuda")
+    pat.prolong_phys(torch.from_numpy(coarse).cuda(), gc.dx, fine, gf.dx)
+    ref = optim.prolong_phys(coarse.astype(np.float64), gc.dx, gf.ny, gf.nx, gf.dx)
+    assert np.abs(fine.cpu().numpy() - ref).max() < 1e-3
+
+
 def test_time_interp(torch):
     from paper_2505_08482_amd import pat
     rng = np.random.default_rng(3)

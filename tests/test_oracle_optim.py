@@ -86,6 +86,33 @@ def test_prolong_reproduces_affine_and_constant_fields():
     assert fr.min() >= r.min() - 1e-15 and fr.max() <= r.max() + 1e-15
 
 
+def test_prolong_phys_between_grids_of_different_extent():
+    """Table 1's levels differ in physical extent: a coarse 39-px grid at
+    0.5263 mm onto an 89-px grid at 0.2273 mm (the target square of both).
+    An affine field in physical coordinates is reproduced exactly wherever the
+    fine pixel lies inside the coarse pixel centres; outside, the value is the
+    clamped edge value; constants are kept everywhere."""
+    nc, dxc, nf, dxf = 39, 0.5263e-3, 125, 0.2273e-3
+    xc = (np.arange(nc) + 0.5 - nc / 2) * dxc
+    xf = (np.arange(nf) + 0.5 - nf / 2) * dxf
+    Xc, Yc = np.meshgrid(xc, xc)
+    Xf, Yf = np.meshgrid(xf, xf)
+    affine = lambda X, Y: 1450.0 + 2.0e4 * X - 3.0e4 * Y
+    fine = optim.prolong_phys(np.stack([affine(Xc, Yc), np.full((nc, nc), 7.0)]), dxc, nf, nf, dxf)
+    inside = (np.abs(Xf) <= xc.max()) & (np.abs(Yf) <= xc.max())
+    assert inside.sum() > 0.4 * nf * nf
+    assert np.allclose(fine[0][inside], affine(Xf, Yf)[inside], rtol=0, atol=1e-9)
+    assert np.all(fine[1] == 7.0)
+    # beyond the last coarse centre along x (and inside along y) the x-edge value is held
+    col = np.argmax(xf > xc.max())
+    rows = np.abs(xf) <= xc.max()
+    assert np.allclose(fine[0][rows, col:], affine(xc.max(), Yf[rows, col:]), atol=1e-9)
+    # a grid of the same extent reduces to the same-extent prolongation (16 -> 32 pixels)
+    rng = np.random.default_rng(3)
+    r = rng.uniform(0, 1, (2, 16, 16))
+    assert np.allclose(optim.prolong_phys(r, 2.0e-4, 32, 32, 1.0e-4), optim.prolong(r, 32, 32), atol=1e-15)
+
+
 def test_time_interp_exact_for_piecewise_linear_and_decimation():
     rng = np.random.default_rng(2)
     y = rng.standard_normal((2, 41, 3))

@@ -76,3 +76,49 @@ def test_noise_is_one_percent_of_peak_to_peak():
         assert abs(np.std(noisy[k] - clean[k]) / sigma[k] - 1.0) < 0.02
     noisy2, _ = I.add_noise(clean, seed=123)
     assert np.array_equal(noisy, noisy2)
+
+
+def test_paper_grids_reproduce_table1_totals_and_duration():
+    """The FFT grids built from Table 1's rows: totals 375 (data) and 81, 125,
+    125, 175, 243 (reconstruction), each a product of 3, 5 and 7; spacing dz;
+    all covering the table's common duration."""
+    rows = {r[0]: r for r in _rows()}
+    expect = {"data": 375, "mg1": 81, "mg2": 125, "mg3": 125, "mg4": 175, "mg5": 243}
+    for name, n in expect.items():
+        g = I.paper_grid(name)
+        assert g.nx == g.ny == n, name
+        assert abs(g.dx - rows[name][1]) <= 1e-12 and g.pml == rows[name][4]
+        assert abs((g.nt - 1) * g.dt - 21.15e-6) <= g.dt, name
+
+
+def test_square_array_geometry():
+    """236 sensors, 59 per side, 0.2 mm outside every side of the 20 mm target
+    square, evenly spaced along the perimeter, inside the non-PML region of
+    every Table 1 grid."""
+    xy = I.square_array()
+    assert xy.shape == (236, 2)
+    cheb = np.max(np.abs(xy), axis=1)
+    assert np.allclose(cheb, 10.2e-3, atol=1e-15)
+    for side in ((xy[:, 1] == -10.2e-3), (xy[:, 0] == 10.2e-3), (xy[:, 1] == 10.2e-3), (xy[:, 0] == -10.2e-3)):
+        assert side.sum() == 59
+    # walking the perimeter, consecutive sensors are one spacing apart (corners included)
+    step = np.sum(np.abs(np.diff(np.vstack([xy, xy[:1]]), axis=0)), axis=1)   # L1 = arc length here
+    assert np.allclose(step, 4 * 20.4e-3 / 236, rtol=1e-12)
+    for name in ("data", "mg1", "mg2", "mg3", "mg4", "mg5"):
+        g = I.paper_grid(name)
+        assert np.all(np.abs(xy) < (g.nx / 2 - g.pml - 1) * g.dx), name
+
+
+def test_nine_disc_stand_in():
+    g = I.paper_grid("mg5")
+    c, p0 = I.nine_disc_phantom(g, 4)
+    c2, p02 = I.nine_disc_phantom(g, 4)
+    assert np.array_equal(c, c2) and np.array_equal(p0, p02)
+    assert set(np.unique(c)) == {1430.0, 1580.0}
+    area = (c == 1580.0).sum() * g.dx ** 2
+    assert abs(area / (9 * np.pi * 1.5e-3 ** 2) - 1.0) < 0.1
+    assert set(np.unique(p0)) == {0.0, 10.0}
+    wl = I.paper_level("mg5", 4)
+    assert np.all(p0[:, ~wl.mask()] == 0.0)
+    # the first initial pressure does not depend on K
+    assert np.array_equal(I.nine_disc_phantom(g, 1)[1][0], p0[0])
