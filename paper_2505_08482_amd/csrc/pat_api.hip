@@ -61,7 +61,7 @@ Trace g_trace;
 // A sampled launch gets the event pair of its slot as the start / stop events
 // of its own dispatch (hipExtLaunchKernelGGL), so the elapsed time between them
 // is the kernel's execution alone, without the queue's dispatch latency.
-hipEvent_t g_launch_ev[2] = {nullptr, nullptr};
+thread_local hipEvent_t g_launch_ev[2] = {nullptr, nullptr};
 
 struct TraceScope {
   TraceScope(int kind, hipStream_t) {
@@ -111,6 +111,7 @@ struct pat_plan {
     uint64_t key[14];
     hipGraphExec_t exec;
     uint64_t last_use;
+    hipEvent_t done;      // recorded after each launch: waited for before the graph is destroyed
   };
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
@@ -492,7 +493,8 @@ int run_steps(pat_plan* p, hipStream_t st, const Args& a, int count, uint64_t ki
   for (auto& e : p->graphs) {
     if (std::memcmp(e.key, key, sizeof(key)) == 0) {
       e.last_use = ++p->graph_clock;
-      return hipGraphLaunch(e.exec, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+      if (hipGraphLaunch(e.exec, st) != hipSuccess) return PAT_EHIP;
+      return hipEventRecord(e.done, st) == hipSuccess ? PAT_OK : PAT_EHIP;
     }
   }
   if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) return PAT_EHIP;
@@ -515,6 +517,8 @@ int run_steps(pat_plan* p, hipStream_t st, const Args& a, int count, uint64_t ki
                                 [](const pat_plan::GraphEntry& x, const pat_plan::GraphEntry& y) {
                                   return x.last_use < y.last_use;
                                 });
+    (void)hipEventSynchronize(lru->done);   // it may still be running
+    (void)hipEventDestroy(lru->done);
     (void)hipGraphExecDestroy(lru->exec);
     p->graphs.erase(lru);
   }
@@ -522,8 +526,23 @@ int run_steps(pat_plan* p, hipStream_t st, const Args& a, int count, uint64_t ki
   std::memcpy(ent.key, key, sizeof(key));
   ent.exec = exec;
   ent.last_use = ++p->graph_clock;
+  if (hipEventCreateWithFlags(&ent.done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    return PAT_EHIP;
+  }
   p->graphs.push_back(ent);
-  return hipGraphLaunch(exec, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+  if (hipGraphLaunch(exec, st) != hipSuccess) return PAT_EHIP;
+  return hipEventRecord(ent.done, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+// Destroy a plan's captured graphs once their last launches have finished.
+void drop_graphs(pat_plan* p) {
+  for (auto& e : p->graphs) {
+    (void)hipEventSynchronize(e.done);
+    (void)hipEventDestroy(e.done);
+    (void)hipGraphExecDestroy(e.exec);
+  }
+  p->graphs.clear();
 }
 
 constexpr int kChunk = 32;   // time steps per captured graph in store-all runs
@@ -830,8 +849,7 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
 
 int pat_plan_destroy(pat_plan* p) {
   if (!p) return PAT_EINVAL;
-  for (auto& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
-  p->graphs.clear();
+  drop_graphs(p);
   if (p->cap) (void)hipStreamDestroy(p->cap);
   if (p->dev) (void)hipFree(p->dev);
   delete p;
@@ -1064,8 +1082,7 @@ int pat_lbfgs_direction(int64_t n, const float* g, int32_t np, const float* cons
 int pat_plan_set_tile(pat_plan* p, int32_t col_tile) {
   if (!p || (col_tile != 0 && col_tile != 8)) return PAT_EINVAL;
   if (col_tile != p->col_tile) {   // captured graphs hold the old kernels
-    for (auto& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
-    p->graphs.clear();
+    drop_graphs(p);
     p->col_tile = col_tile;
   }
   return PAT_OK;
@@ -1103,8 +1120,8 @@ int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams
     jb.a.SC = at<float2>(ws, jb.L.SC); jb.a.SD = at<float2>(ws, jb.L.SD);
     jb.a.ctl = jb.f.ctl;
     jb.cost = (double)p->K * p->g.nx * p->g.ny * p->g.nt;
-    p->recorded = false;
   }
+  for (auto& jb : jobs) jb.pr.plan->recorded = false;   // the batch overwrites every workspace
   const int ns = std::min(nstreams, nprob);
   PAT_TRY(pool_streams(ns));
   // schedule: longest problems first, each onto the least-loaded stream

@@ -203,3 +203,35 @@ def test_traced_launches_equal_plain_and_time_every_pass():
     for kind, (n, ms) in tr.items():
         print(f"[trace] {kind}: {n} launches, {ms / max(n, 1) * 1000:.2f} us")
         assert n > 0 and ms > 0.0
+
+
+def test_graph_cache_eviction_keeps_results():
+    """One plan driven through many distinct step-run shapes (checkpoint
+    intervals) overflows its cache of captured graphs; evicted graphs are
+    destroyed only after their launches finished and every result stays
+    bit-identical to store-all."""
+    import torch
+    from paper_2505_08482_amd import pat
+    wl = _wl(n=64, K=2, nt=97, m=32)
+    c, p0, r = _inputs(wl, seed=9)
+    announce("graph cache eviction")
+    plan = pat.Plan(wl.grid, wl.K, wl.sensors)
+    dev = "cuda"
+    tc, tp0, tr = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (c, p0, r))
+    outs = []
+    for s in (0, 3, 5, 6, 7, 9, 10, 11, 13, 3, 0):
+        ws = plan.workspace(s)
+        data = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
+        gp0 = torch.empty(plan.field_shape, dtype=torch.float32, device=dev)
+        gc = torch.empty((wl.grid.ny, wl.grid.nx), dtype=torch.float32, device=dev)
+        plan.forward(tc, tp0, data, ws, ckpt_every=s, record=True)
+        plan.adjoint_gradient(tc, tp0, tr, gp0, gc, ws)
+        torch.cuda.synchronize()
+        outs.append((s, data.cpu().numpy(), gp0.cpu().numpy(), gc.cpu().numpy()))
+        del ws
+    plan.close()
+    ref = outs[0]
+    for s, d, gp, gcc in outs[1:]:
+        assert np.array_equal(d, ref[1]), s
+        assert np.array_equal(gp, ref[2]), s
+        assert np.array_equal(gcc, ref[3]), s
