@@ -235,3 +235,44 @@ def test_graph_cache_eviction_keeps_results():
         assert np.array_equal(d, ref[1]), s
         assert np.array_equal(gp, ref[2]), s
         assert np.array_equal(gcc, ref[3]), s
+
+
+def test_error_paths_through_the_abi():
+    """The library refuses, without launching anything: an adjoint before any
+    recorded forward, with another workspace, other c / p0 buffers, or a
+    workspace too small; a forward into a too-small workspace.  A refused call
+    leaves the recorded state usable."""
+    import torch
+    from paper_2505_08482_amd import pat
+    wl = _wl(n=64, K=2, nt=40, m=16)
+    c, p0, r = _inputs(wl, seed=2)
+    announce("error paths")
+    plan = pat.Plan(wl.grid, wl.K, wl.sensors)
+    dev = "cuda"
+    tc, tp0, tr = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (c, p0, r))
+    data = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
+    gp0 = torch.empty(plan.field_shape, dtype=torch.float32, device=dev)
+    gc = torch.empty((wl.grid.ny, wl.grid.nx), dtype=torch.float32, device=dev)
+    ws = plan.workspace(0)
+    ws2 = plan.workspace(0)
+
+    def status(fn):
+        try:
+            fn()
+        except pat.PatError as e:
+            return e.status
+        return pat.PAT_OK
+
+    EW = pat.PAT_EWORKSPACE
+    assert status(lambda: plan.adjoint_gradient(tc, tp0, tr, gp0, gc, ws)) == EW
+    small = torch.empty(plan.workspace_size(0) - 256, dtype=torch.uint8, device=dev)
+    assert status(lambda: plan.forward(tc, tp0, data, small, record=True)) == EW
+    plan.forward(tc, tp0, data, ws, record=True)
+    assert status(lambda: plan.adjoint_gradient(tc, tp0, tr, gp0, gc, ws2)) == EW
+    assert status(lambda: plan.adjoint_gradient(tc.clone(), tp0, tr, gp0, gc, ws)) == EW
+    assert status(lambda: plan.adjoint_gradient(tc, tp0.clone(), tr, gp0, gc, ws)) == EW
+    plan.adjoint_gradient(tc, tp0, tr, gp0, gc, ws)   # the recorded state survived the refusals
+    ref = gpu_forward_adjoint(wl, c, p0, resid32=r)
+    torch.cuda.synchronize()
+    assert np.array_equal(gp0.cpu().numpy(), ref["g_p0"]) and np.array_equal(gc.cpu().numpy(), ref["g_c"])
+    plan.close()

@@ -42,3 +42,18 @@ def test_host_side_argument_checks():
     assert L.pat_project_update(-1, None, None, 1.0, None, None, 0.0, 1.0, None) == pat.PAT_EINVAL
     assert L.pat_prolong(0, None, 1, 1, None, 1, 1, None) == pat.PAT_EINVAL
     assert pat.status_string(pat.PAT_EWORKSPACE).startswith("workspace")
+    g = pat.pat_grid(64, 64, 10, 8, 1e-4, 1e-8, 1600.0, 1000.0, 2.0)
+    assert L.pat_plan_create(ctypes.byref(g), 65, 1, xy, ctypes.byref(h)) == pat.PAT_EUNSUPPORTED   # K > 64
+    far = (ctypes.c_double * 2)(0.0, 40e-4)                                                     # off the grid
+    assert L.pat_plan_create(ctypes.byref(g), 1, 1, far, ctypes.byref(h)) == pat.PAT_EINVAL
+    nan = (ctypes.c_double * 2)(float("nan"), 0.0)
+    assert L.pat_plan_create(ctypes.byref(g), 1, 1, nan, ctypes.byref(h)) == pat.PAT_EINVAL
+    g = pat.pat_grid(64, 64, 10, 32, 1e-4, 1e-8, 1600.0, 1000.0, 2.0)     # PML covers the grid
+    assert L.pat_plan_create(ctypes.byref(g), 1, 1, xy, ctypes.byref(h)) == pat.PAT_EINVAL
+    assert L.pat_prolong_phys(1, None, 4, 4, 1e-4, None, 8, 8, 5e-5, None) == pat.PAT_EINVAL
+    dummy = ctypes.c_void_p(1)
+    assert L.pat_prolong_phys(1, dummy, 4, 4, 0.0, dummy, 8, 8, 5e-5, None) == pat.PAT_EINVAL
+    assert L.pat_batch_gradient(0, None, 1, None) == pat.PAT_EINVAL
+    assert L.pat_batch_gradient(1, dummy, 17, None) == pat.PAT_EINVAL
+    assert L.pat_trace_start(0) == pat.PAT_EINVAL
+    assert L.pat_plan_set_tile(None, 0) == pat.PAT_EINVAL
