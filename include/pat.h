@@ -22,6 +22,11 @@
  *    failing call enqueues nothing.  pat_status_string() names a code.
  *  - A plan and its internal scratch belong to one stream at a time: calls on
  *    one plan that overlap on different streams race.
+ *  - Environment: PAT_NO_GRAPHS (any value) launches every pass directly
+ *    instead of replaying captured step graphs (same bits);
+ *    PAT_GENERIC_KERNELS (any value, read by pat_plan_create) selects the
+ *    any-radix LDS kernels also for power-of-two grids (same results to
+ *    float32 rounding).
  */
 #ifndef PAT_H
 #define PAT_H
