@@ -16,6 +16,7 @@ import os
 import numpy as np
 import pytest
 
+from oracle import kspace
 from paper_2505_08482_amd import inputs as I
 from gpu_helpers import announce, gpu_forward_adjoint, oracle_forward_adjoint, observed_data, rel_l2
 
@@ -56,7 +57,6 @@ def test_batch_equals_single_runs_bitwise(K):
     full = gpu_forward_adjoint(wl, c, p0, resid32=r)
     gc_sum = np.zeros(full["g_c"].shape, dtype=np.float64)
     for k in range(wl.K):
-        w1 = dataclasses.replace(wl, K=1)
         one = gpu_forward_adjoint(w1, c, p0[k:k + 1], resid32=np.ascontiguousarray(r[k:k + 1]))
         assert np.array_equal(one["data"][0], full["data"][k])
         assert np.array_equal(one["g_p0"][0], full["g_p0"][k])
@@ -121,6 +121,33 @@ def test_w1_full_size_properties():
     assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
     assert torch.isfinite(gc).all()
     plan.close()
+
+
+def test_w1_full_size_dataset_vs_oracle():
+    """The benchmark's launch configuration itself (512^2, K = 8, 4000 samples,
+    the true heterogeneous c): dataset 0's sensor traces and g_p0 against the
+    float64 oracle run on that dataset alone (the datasets are independent given
+    c; g_c, a sum over all eight, is covered by the dot test above)."""
+    import torch
+    from paper_2505_08482_amd import pat
+    wl = I.w1()
+    g = wl.grid
+    c_np, p0_np = I.phantoms(wl, 3)
+    c32 = c_np.astype(np.float32)
+    p032 = p0_np.astype(np.float32)
+    rng = np.random.default_rng(31)
+    r32 = rng.standard_normal((wl.K, g.nt, wl.m)).astype(np.float32)
+    announce("w1 full size gpu K=8")
+    gpu = gpu_forward_adjoint(wl, c32, p032, resid32=r32)
+    announce("w1 full size oracle dataset 0")
+    data, hist = kspace.forward(g, wl.sensors, c32.astype(np.float64), p032[:1].astype(np.float64))
+    gp0, _ = kspace.adjoint_gradient(g, wl.sensors, c32.astype(np.float64), p032[:1].astype(np.float64),
+                                     r32[:1].astype(np.float64), hist)
+    del hist
+    e_d = rel_l2(gpu["data"][0], data[0])
+    e_p = rel_l2(gpu["g_p0"][0], gp0[0])
+    print(f"[w1 parity] data {e_d:.2e} g_p0 {e_p:.2e}", flush=True)
+    assert e_d <= 1e-4 and e_p <= 1e-3
 
 
 def test_generic_and_power_of_two_kernels_agree():
