@@ -13,6 +13,8 @@ Contents
              data misfit of eq. (4) and its exact discrete adjoint gradient
              (eqs. (5)-(9), taken as the gradient of the discrete objective).
 ``sensors``  point-sensor sampling operator of Sec. 2.2 and its transpose.
+``prior``    Ornstein-Uhlenbeck prior terms of eq. (4) (Sec. 4.1.2): dense
+             exponential correlation over the reconstruction pixels, Cholesky.
 ``optim``    bound projection (eq. (11)), L-BFGS two-loop recursion (Alg. 1),
              projected quasi-Newton step with backtracking (eq. (10)),
              multigrid prolongation (Sec. 3.1) and data time resampling
