@@ -171,8 +171,9 @@ def paper_geometry(iters: int = 40, levels=("mg1", "mg2", "mg3", "mg4")):
     data simulated on the 375^2 data grid (not a reconstruction grid) with 1 %
     noise, and multigrid reconstructions over Table 1's grids 1-4 with all four
     datasets (K = 4) and with the first alone (K = 1, the paper's reference
-    approach); c in [1300, 1800] m/s, starting at 1505 m/s, 1430 m/s held
-    outside the target square.  E_c and E_p0 of dataset 1 on the finest level."""
+    approach), each with bounds only and with the paper's Ornstein-Uhlenbeck
+    prior; c in [1300, 1800] m/s, starting at 1505 m/s, 1430 m/s held outside
+    the target square.  E_c and E_p0 of dataset 1 on the finest level."""
     import torch
     from paper_2505_08482_amd import pat, recon
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
@@ -188,21 +189,26 @@ def paper_geometry(iters: int = 40, levels=("mg1", "mg2", "mg3", "mg4")):
     plan.close()
     del ws
     noisy, sigma = I.add_noise(data.cpu().numpy().astype(np.float64), seed=6500)
+    del data
+    torch.cuda.empty_cache()
     out = {"data_grid": wd.grid.nx, "data_nt": wd.grid.nt, "data_seconds": round(t_data, 3),
            "sensors": wd.m, "levels": [I.paper_grid(n).nx for n in levels], "iters_per_level": iters}
-    for K in (4, 1):
+    # the paper's prior (Sec. 4.1.2): tau = 1.5 mm, means at the middle and standard
+    # deviations a quarter of the true ranges (p0 in [0, 10] Pa, c in [1430, 1580] m/s)
+    ou = {"tau": 1.5e-3, "eta_p0": 5.0, "sigma_p0": 2.5, "eta_c": 1505.0, "sigma_c": 37.5}
+    for K, use_prior in ((4, False), (1, False), (4, True), (1, True)):
         lv = [I.paper_level(n, K) for n in levels]
         t = time.perf_counter()
         res = recon.multigrid(lv, T(noisy[:K]), wd.grid.dt, T(1.0 / sigma[:K]),
                               lambda wl: T(I.nine_disc_phantom(wl.grid, 1)[0]), c_lo=1300.0, c_hi=1800.0,
-                              iters=iters, c_init=1505.0, c_fixed=1430.0)
+                              iters=iters, c_init=1505.0, c_fixed=1430.0, prior=ou if use_prior else None)
         secs = time.perf_counter() - t
         fine = lv[-1]
         p0t = I.nine_disc_phantom(fine.grid, 1)[1][0]
         m = fine.mask()
         p0r = res["p0"][0].cpu().numpy().astype(np.float64)
         e_p0 = 100.0 * float(np.linalg.norm((p0r - p0t)[m]) / np.linalg.norm(p0t[m]))
-        out[f"K{K}"] = {"E_c_percent": round(res["E_c"], 3), "E_p0_1_percent": round(e_p0, 2),
+        out[f"K{K}" + ("_ou_prior" if use_prior else "")] = {"E_c_percent": round(res["E_c"], 3), "E_p0_1_percent": round(e_p0, 2),
                         "seconds": round(secs, 2), "iterations": [r.iters for r in res["levels"]],
                         "evals": [r.evals for r in res["levels"]]}
     return out

@@ -188,6 +188,35 @@ typedef struct pat_problem {
  * workspace (PAT_EINVAL otherwise). */
 int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams, void* stream);
 
+/* Eq. (4) prior terms with the Ornstein-Uhlenbeck covariance of Sec. 4.1.2:
+ * Gamma_z = sigma_z^2 Xi, Xi_ij = exp(-|r_i - r_j| / tau), over the pixels
+ * r_i (spacing dx, metres) of the reconstruction domain given by a host mask
+ * [ny][nx] (nonzero = in the domain; NULL = the whole grid).  An opaque object
+ * holds the operator: products with Xi are exact (FFT convolution on a
+ * periodic embedding of the mask's bounding box, L >= 2 * box side - 1 from
+ * the supported transform lengths); Xi^{-1} is applied by preconditioned
+ * conjugate gradients.  PAT_EUNSUPPORTED when the box needs L > 512;
+ * PAT_EINVAL for an empty mask or non-positive sizes.  Vectors are device
+ * arrays [nvec][ny][nx]; entries outside the mask are ignored on input and
+ * written as zero. */
+typedef struct pat_ou pat_ou;
+int pat_ou_create(int32_t ny, int32_t nx, double dx, double tau, const uint8_t* mask, pat_ou** out);
+int pat_ou_destroy(pat_ou* ou);
+/* bytes of caller-owned device scratch for nvec vectors */
+int pat_ou_scratch_bytes(const pat_ou* ou, int32_t nvec, size_t* bytes);
+/* out = Xi v on the mask (the exact product; for tests and diagnostics) */
+int pat_ou_apply(pat_ou* ou, int32_t nvec, const float* v, float* out, void* scratch, size_t scratch_bytes,
+                 void* stream);
+/* For every vector z_v with mean eta[v] and 1/sigma_v^2 = inv_var[v] (device
+ * float arrays [nvec]): grad_v = inv_var[v] Xi^{-1} (z_v - eta[v]) and
+ * *J (device double) = sum_v 1/2 inv_var[v] (z_v - eta[v])^T Xi^{-1} (z_v - eta[v]).
+ * Conjugate gradients stop when every residual is below tol times its
+ * right-hand side (checked every 8 iterations) or after maxit iterations;
+ * *iters (host, may be NULL) receives the count.  Synchronizes the stream. */
+int pat_ou_prior(pat_ou* ou, int32_t nvec, const float* z, const float* eta, const float* inv_var, float* grad,
+                 double* J, double tol, int32_t maxit, void* scratch, size_t scratch_bytes, int32_t* iters,
+                 void* stream);
+
 /* Kernel timing (diagnostics).  Kinds of fused pass, in time-step order:
  * forward column GRAD, row U, column DIV, row RHO; adjoint column SUMM, row
  * RHO, column GRAD, row U. */

@@ -15,6 +15,7 @@
 #include "vec_kernels.hpp"
 #include "wave_kernels.hpp"
 #include "fast_kernels.hpp"
+#include "prior_kernels.hpp"
 
 using namespace pat;
 
@@ -690,6 +691,136 @@ int job_unit(BatchJob& j, hipStream_t st) {
 // ============================================================================
 // C ABI
 // ============================================================================
+struct pat_ou {
+  int ny = 0, nx = 0;                 // grid of the vectors
+  int oy = 0, ox = 0, nby = 0, nbx = 0;   // bounding box of the mask
+  int L = 0;                          // periodic embedding (L x L, L >= 2 max(nby, nbx) - 1)
+  void* dev = nullptr;                // twiddles, spectra, box mask
+  float2* tw = nullptr;
+  float* s_op = nullptr;              // spectrum of the embedded kernel (exact products)
+  float* s_pre = nullptr;             // reciprocal spectrum, floored (preconditioner)
+  uint8_t* mask = nullptr;            // [nby][nbx]
+};
+
+namespace {
+
+// Scratch of an OU solve with nvec right-hand sides.
+struct OuLayout {
+  size_t b, x, r, z, p, Ap, W, partial, sc, dots, total;
+};
+OuLayout ou_layout(const pat_ou* o, int nvec) {
+  OuLayout L{};
+  const size_t nb = (size_t)nvec * o->nby * o->nbx * sizeof(float);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  L.b = take(nb); L.x = take(nb); L.r = take(nb); L.z = take(nb); L.p = take(nb); L.Ap = take(nb);
+  L.W = take((size_t)nvec * o->nby * o->L * sizeof(float2));
+  L.partial = take((size_t)nvec * ou::DOT_BLOCKS * sizeof(double));
+  L.sc = take((size_t)5 * nvec * sizeof(double));
+  L.dots = take((size_t)nvec * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// out = P_M C P_M v for the circulant C with spectrum S (box vectors).
+int ou_circ(const pat_ou* o, hipStream_t st, int nvec, const float* v, const float* S, float2* W, float* out) {
+  const float scale = 1.0f / ((float)o->L * (float)o->L);
+  switch (o->L) {
+#define X(N)                                                                                                  \
+  case N: {                                                                                                   \
+    constexpr int T = Threads<N>::v;                                                                          \
+    const int rows = nvec * o->nby, cols = nvec * N;                                                          \
+    hipLaunchKernelGGL(ou::k_rows_fwd<N>, dim3((rows + 256 / T - 1) / (256 / T)), dim3(256), 0, st, v, nvec,  \
+                       o->nby, o->nbx, o->tw, W);                                                             \
+    hipLaunchKernelGGL(ou::k_cols<N>, dim3((cols + 256 / T - 1) / (256 / T)), dim3(256), 0, st, W, nvec,      \
+                       o->nby, S, o->tw);                                                                     \
+    hipLaunchKernelGGL(ou::k_rows_inv<N>, dim3((rows + 256 / T - 1) / (256 / T)), dim3(256), 0, st, W, nvec,  \
+                       o->nby, o->nbx, o->mask, o->tw, scale, out);                                           \
+    return last_error();                                                                                      \
+  }
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+}
+
+// dots[vec] = a_vec . b_vec (box vectors, fixed order)
+int ou_dots(const pat_ou* o, hipStream_t st, int nvec, const float* a, const float* b, double* partial,
+            double* out) {
+  const int64_t n = (int64_t)o->nby * o->nbx;
+  hipLaunchKernelGGL(ou::k_dots, dim3(ou::DOT_BLOCKS, nvec), dim3(ou::DOT_THREADS), 0, st, a, b, n, partial);
+  PAT_TRY(last_error());
+  hipLaunchKernelGGL(ou::k_dot_final, dim3((nvec + 63) / 64), dim3(64), 0, st, partial, nvec, out);
+  return last_error();
+}
+
+// x = Xi_M^{-1} b by preconditioned conjugate gradients (box vectors in the scratch).
+int ou_pcg(const pat_ou* o, hipStream_t st, int nvec, char* ws, const OuLayout& L, double tol, int maxit,
+           int* iters) {
+  float* b = reinterpret_cast<float*>(ws + L.b);
+  float* x = reinterpret_cast<float*>(ws + L.x);
+  float* r = reinterpret_cast<float*>(ws + L.r);
+  float* z = reinterpret_cast<float*>(ws + L.z);
+  float* p = reinterpret_cast<float*>(ws + L.p);
+  float* Ap = reinterpret_cast<float*>(ws + L.Ap);
+  float2* W = reinterpret_cast<float2*>(ws + L.W);
+  double* partial = reinterpret_cast<double*>(ws + L.partial);
+  double* sc = reinterpret_cast<double*>(ws + L.sc);
+  double* dots = reinterpret_cast<double*>(ws + L.dots);
+  const int64_t n = (int64_t)o->nby * o->nbx, tot = n * nvec;
+  const size_t vb = (size_t)tot * sizeof(float);
+  PAT_TRY(fill_zero(st, x, vb));
+  PAT_TRY(copy_dev(st, b, r, vb));
+  std::vector<double> bb((size_t)nvec), rr((size_t)nvec);
+  PAT_TRY(ou_dots(o, st, nvec, b, b, partial, dots));
+  if (hipMemcpyAsync(bb.data(), dots, nvec * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return PAT_EHIP;
+  PAT_TRY(ou_circ(o, st, nvec, r, o->s_pre, W, z));
+  PAT_TRY(copy_dev(st, z, p, vb));
+  PAT_TRY(ou_dots(o, st, nvec, r, z, partial, sc));   // rz
+  const int vb1 = (nvec + 63) / 64;
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    PAT_TRY(ou_circ(o, st, nvec, p, o->s_op, W, Ap));
+    PAT_TRY(ou_dots(o, st, nvec, p, Ap, partial, sc + nvec));   // pAp
+    hipLaunchKernelGGL(ou::k_cg_alpha, dim3(vb1), dim3(64), 0, st, sc, nvec);
+    hipLaunchKernelGGL(ou::k_cg_update, dim3(grid_blocks(tot)), dim3(256), 0, st, nvec, n, sc, p, Ap, x, r);
+    PAT_TRY(last_error());
+    if (it % 8 == 0 || it == maxit) {   // convergence test on the host every 8 iterations
+      PAT_TRY(ou_dots(o, st, nvec, r, r, partial, dots));
+      if (hipMemcpyAsync(rr.data(), dots, nvec * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return PAT_EHIP;
+      bool done = true;
+      for (int v = 0; v < nvec; ++v) done = done && rr[v] <= tol * tol * bb[v];
+      if (done) break;
+    }
+    PAT_TRY(ou_circ(o, st, nvec, r, o->s_pre, W, z));
+    PAT_TRY(ou_dots(o, st, nvec, r, z, partial, sc + 4 * nvec));   // rz_new
+    hipLaunchKernelGGL(ou::k_cg_beta, dim3(vb1), dim3(64), 0, st, sc, nvec);
+    hipLaunchKernelGGL(ou::k_cg_dir, dim3(grid_blocks(tot)), dim3(256), 0, st, nvec, n, sc, z, p);
+    PAT_TRY(last_error());
+  }
+  if (iters) *iters = std::min(it, maxit);
+  return PAT_OK;
+}
+
+// 1/2 sum_v w_v dots[v] -> *J (one thread, fixed order)
+__global__ void k_ou_energy(const double* __restrict__ dots, const float* __restrict__ w, int nvec, double* J) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int v = 0; v < nvec; ++v) s += 0.5 * (double)w[v] * dots[v];
+    *J = s;
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pat_status_string(int s) {
@@ -1204,6 +1335,151 @@ int pat_trace_read(int32_t kind, int64_t* count, double* total_ms) {
   *count = g_trace.used[kind];
   *total_ms = tot;
   return PAT_OK;
+}
+
+
+int pat_ou_create(int32_t ny, int32_t nx, double dx, double tau, const uint8_t* mask, pat_ou** out) {
+  if (!out || ny <= 0 || nx <= 0 || !(dx > 0.0) || !(tau > 0.0)) return PAT_EINVAL;
+  *out = nullptr;
+  // bounding box of the mask
+  int y0 = ny, y1 = -1, x0 = nx, x1 = -1;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x)
+      if (!mask || mask[(size_t)y * nx + x]) {
+        y0 = std::min(y0, y); y1 = std::max(y1, y); x0 = std::min(x0, x); x1 = std::max(x1, x);
+      }
+  if (y1 < 0) return PAT_EINVAL;   // empty mask
+  const int nby = y1 - y0 + 1, nbx = x1 - x0 + 1;
+  const int need = 2 * std::max(nby, nbx) - 1;
+  static const int sizes[] = {32, 36, 40, 48, 64, 81, 84, 96, 125, 128, 160, 175, 192, 243, 256, 375, 384, 512};
+  int L = 0;
+  for (int cand : sizes)
+    if (cand >= need) { L = cand; break; }
+  if (!L) return PAT_EUNSUPPORTED;
+  // twiddles and the spectrum of the kernel on the wrapped offsets (float64 cosine sums:
+  // the embedded kernel is even along both axes, so its DFT is real)
+  std::vector<float2> tw((size_t)L);
+  std::vector<double> cosv((size_t)L);
+  for (int j = 0; j < L; ++j) {
+    tw[j] = make_float2((float)std::cos(2 * M_PI * j / L), (float)-std::sin(2 * M_PI * j / L));
+    cosv[j] = std::cos(2 * M_PI * j / L);
+  }
+  std::vector<double> e((size_t)L * L), A((size_t)L * L, 0.0), S((size_t)L * L, 0.0);
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      const double dy = std::min(y, L - y), dxw = std::min(x, L - x);
+      e[(size_t)y * L + x] = std::exp(-dx * std::sqrt(dy * dy + dxw * dxw) / tau);
+    }
+  for (int y = 0; y < L; ++y)
+    for (int k = 0; k < L; ++k) {
+      double acc = 0.0;
+      for (int x = 0; x < L; ++x) acc += e[(size_t)y * L + x] * cosv[((size_t)k * x) % L];
+      A[(size_t)y * L + k] = acc;
+    }
+  for (int ky = 0; ky < L; ++ky)
+    for (int kx = 0; kx < L; ++kx) {
+      double acc = 0.0;
+      for (int y = 0; y < L; ++y) acc += A[(size_t)y * L + kx] * cosv[((size_t)ky * y) % L];
+      S[(size_t)ky * L + kx] = acc;
+    }
+  double smax = 0.0;
+  for (double v : S) smax = std::max(smax, v);
+  std::vector<float> sop((size_t)L * L), spre((size_t)L * L);
+  for (size_t i = 0; i < S.size(); ++i) {
+    sop[i] = (float)S[i];
+    spre[i] = (float)(1.0 / std::max(S[i], 1e-6 * smax));
+  }
+  std::vector<uint8_t> bm((size_t)nby * nbx);
+  for (int y = 0; y < nby; ++y)
+    for (int x = 0; x < nbx; ++x) bm[(size_t)y * nbx + x] = !mask || mask[(size_t)(y0 + y) * nx + x0 + x] ? 1 : 0;
+  const size_t o_tw = 0, o_op = align256(L * sizeof(float2)), o_pre = o_op + align256((size_t)L * L * 4),
+               o_m = o_pre + align256((size_t)L * L * 4), total = o_m + align256(bm.size());
+  pat_ou* o = new (std::nothrow) pat_ou();
+  if (!o) return PAT_EHIP;
+  if (hipMalloc(&o->dev, total) != hipSuccess) {
+    delete o;
+    return PAT_EHIP;
+  }
+  std::vector<char> host(total, 0);
+  std::memcpy(host.data() + o_tw, tw.data(), tw.size() * sizeof(float2));
+  std::memcpy(host.data() + o_op, sop.data(), sop.size() * 4);
+  std::memcpy(host.data() + o_pre, spre.data(), spre.size() * 4);
+  std::memcpy(host.data() + o_m, bm.data(), bm.size());
+  if (hipMemcpy(o->dev, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(o->dev);
+    delete o;
+    return PAT_EHIP;
+  }
+  char* d = static_cast<char*>(o->dev);
+  o->tw = reinterpret_cast<float2*>(d + o_tw);
+  o->s_op = reinterpret_cast<float*>(d + o_op);
+  o->s_pre = reinterpret_cast<float*>(d + o_pre);
+  o->mask = reinterpret_cast<uint8_t*>(d + o_m);
+  o->ny = ny; o->nx = nx; o->oy = y0; o->ox = x0; o->nby = nby; o->nbx = nbx; o->L = L;
+  *out = o;
+  return PAT_OK;
+}
+
+int pat_ou_destroy(pat_ou* o) {
+  if (!o) return PAT_EINVAL;
+  if (o->dev) (void)hipFree(o->dev);
+  delete o;
+  return PAT_OK;
+}
+
+int pat_ou_scratch_bytes(const pat_ou* o, int32_t nvec, size_t* bytes) {
+  if (!o || nvec <= 0 || !bytes) return PAT_EINVAL;
+  *bytes = ou_layout(o, nvec).total;
+  return PAT_OK;
+}
+
+int pat_ou_apply(pat_ou* o, int32_t nvec, const float* v, float* out, void* scratch, size_t scratch_bytes,
+                 void* stream) {
+  if (!o || nvec <= 0 || !v || !out || !scratch) return PAT_EINVAL;
+  const OuLayout L = ou_layout(o, nvec);
+  if (scratch_bytes < L.total) return PAT_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(scratch);
+  float* b = reinterpret_cast<float*>(ws + L.b);
+  float* y = reinterpret_cast<float*>(ws + L.x);
+  const int64_t n = (int64_t)nvec * o->nby * o->nbx;
+  hipLaunchKernelGGL(ou::k_gather, dim3(grid_blocks(n)), dim3(256), 0, st, v, nvec, o->ny, o->nx, o->oy, o->ox,
+                     o->nby, o->nbx, o->mask, 0.0f, nullptr, b);
+  PAT_TRY(last_error());
+  PAT_TRY(ou_circ(o, st, nvec, b, o->s_op, reinterpret_cast<float2*>(ws + L.W), y));
+  const int64_t ng = (int64_t)nvec * o->ny * o->nx;
+  hipLaunchKernelGGL(ou::k_scatter, dim3(grid_blocks(ng)), dim3(256), 0, st, y, nvec, o->ny, o->nx, o->oy, o->ox,
+                     o->nby, o->nbx, nullptr, out);
+  return last_error();
+}
+
+int pat_ou_prior(pat_ou* o, int32_t nvec, const float* z, const float* eta, const float* inv_var, float* grad,
+                 double* J, double tol, int32_t maxit, void* scratch, size_t scratch_bytes, int32_t* iters,
+                 void* stream) {
+  if (!o || nvec <= 0 || !z || !eta || !inv_var || !grad || !J || !scratch || !(tol > 0.0) || maxit <= 0)
+    return PAT_EINVAL;
+  const OuLayout L = ou_layout(o, nvec);
+  if (scratch_bytes < L.total) return PAT_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(scratch);
+  float* b = reinterpret_cast<float*>(ws + L.b);
+  float* x = reinterpret_cast<float*>(ws + L.x);
+  const int64_t n = (int64_t)nvec * o->nby * o->nbx;
+  hipLaunchKernelGGL(ou::k_gather, dim3(grid_blocks(n)), dim3(256), 0, st, z, nvec, o->ny, o->nx, o->oy, o->ox,
+                     o->nby, o->nbx, o->mask, 1.0f, eta, b);
+  PAT_TRY(last_error());
+  int it = 0;
+  PAT_TRY(ou_pcg(o, st, nvec, ws, L, tol, maxit, &it));
+  if (iters) *iters = it;
+  // J = sum_v 1/2 inv_var_v (b_v . x_v); grad = inv_var_v x_v on the grid
+  double* dots = reinterpret_cast<double*>(ws + L.dots);
+  PAT_TRY(ou_dots(o, st, nvec, b, x, reinterpret_cast<double*>(ws + L.partial), dots));
+  hipLaunchKernelGGL(k_ou_energy, dim3(1), dim3(64), 0, st, dots, inv_var, nvec, J);
+  PAT_TRY(last_error());
+  const int64_t ng = (int64_t)nvec * o->ny * o->nx;
+  hipLaunchKernelGGL(ou::k_scatter, dim3(grid_blocks(ng)), dim3(256), 0, st, x, nvec, o->ny, o->nx, o->oy, o->ox,
+                     o->nby, o->nbx, inv_var, grad);
+  return last_error();
 }
 
 }  // extern "C"

@@ -23,6 +23,7 @@ EXPORTS = (
     "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_prolong_phys", "pat_time_interp",
     "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_dot", "pat_status_string",
     "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_batch_gradient",
+    "pat_ou_create", "pat_ou_destroy", "pat_ou_scratch_bytes", "pat_ou_apply", "pat_ou_prior",
 )
 
 PASS_KINDS = ("fwd_col_grad", "fwd_row_u", "fwd_col_div", "fwd_row_rho",
@@ -81,6 +82,11 @@ def lib() -> ctypes.CDLL:
     L.pat_trace_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     L.pat_plan_set_tile.argtypes = [vp, i32]
     L.pat_batch_gradient.argtypes = [i32, vp, i32, vp]
+    L.pat_ou_create.argtypes = [i32, i32, f64, f64, vp, ctypes.POINTER(vp)]
+    L.pat_ou_destroy.argtypes = [vp]
+    L.pat_ou_scratch_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.pat_ou_apply.argtypes = [vp, i32, vp, vp, vp, sz, vp]
+    L.pat_ou_prior.argtypes = [vp, i32, vp, vp, vp, vp, vp, f64, i32, vp, sz, ctypes.POINTER(i32), vp]
     L.pat_status_string.argtypes = [ctypes.c_int]
     L.pat_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -302,3 +308,59 @@ def batch_gradient(jobs, nstreams: int = 8):
         arr[i].ws_bytes = j["ws"].numel()
     _check(lib().pat_batch_gradient(len(jobs), ctypes.cast(arr, ctypes.c_void_p), int(nstreams), _stream()),
            "pat_batch_gradient")
+
+
+class OuPrior:
+    """Ornstein-Uhlenbeck prior operator of eq. (4) (Sec. 4.1.2) over the pixels
+    of ``mask [ny][nx]`` (bool, host; None = the whole grid), spacing ``dx``,
+    correlation length ``tau`` (metres)."""
+
+    def __init__(self, ny: int, nx: int, dx: float, tau: float, mask=None):
+        self.ny, self.nx = int(ny), int(nx)
+        self._mask = None
+        mp = None
+        if mask is not None:
+            m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+            if m.shape != (self.ny, self.nx):
+                raise ValueError("mask shape mismatch")
+            self._mask = m
+            mp = m.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(lib().pat_ou_create(self.ny, self.nx, float(dx), float(tau), mp, ctypes.byref(h)), "pat_ou_create")
+        self._h = h
+        self._scratch = {}
+
+    def scratch(self, nvec: int, device="cuda"):
+        import torch
+        if nvec not in self._scratch:
+            b = ctypes.c_size_t()
+            _check(lib().pat_ou_scratch_bytes(self._h, int(nvec), ctypes.byref(b)), "pat_ou_scratch_bytes")
+            self._scratch[nvec] = torch.empty(b.value, dtype=torch.uint8, device=device)
+        return self._scratch[nvec]
+
+    def apply(self, v, out):
+        """``out = Xi v`` on the mask (``v``, ``out``: [nvec][ny][nx] float32)."""
+        nvec = v.numel() // (self.ny * self.nx)
+        n = nvec * self.ny * self.nx
+        ws = self.scratch(nvec)
+        _check(lib().pat_ou_apply(self._h, nvec, _f32(v, n, "v"), _f32(out, n, "out"), _ptr(ws), ws.numel(),
+                                  _stream()), "pat_ou_apply")
+
+    def prior(self, z, eta, inv_var, grad, J, tol: float = 1e-6, maxit: int = 500) -> int:
+        """Prior terms of eq. (4) for the vectors ``z [nvec][ny][nx]`` (means
+        ``eta [nvec]``, ``inv_var [nvec]`` = 1/sigma^2): fills ``grad`` and the
+        device scalar ``J``; returns the conjugate-gradient iterations."""
+        nvec = z.numel() // (self.ny * self.nx)
+        n = nvec * self.ny * self.nx
+        ws = self.scratch(nvec)
+        it = ctypes.c_int32()
+        _check(lib().pat_ou_prior(self._h, nvec, _f32(z, n, "z"), _f32(eta, nvec, "eta"),
+                                  _f32(inv_var, nvec, "inv_var"), _f32(grad, n, "grad"), _ptr(J), float(tol),
+                                  int(maxit), _ptr(ws), ws.numel(), ctypes.byref(it), _stream()), "pat_ou_prior")
+        return it.value
+
+    def close(self):
+        if self._h:
+            lib().pat_ou_destroy(self._h)
+            self._h = None
+        self._scratch = {}

@@ -3,6 +3,8 @@
 
 * objective and gradient: ``pat_forward`` (recorded) + ``pat_misfit`` +
   ``pat_adjoint_gradient`` (eq. (4) data term, eqs. (5)-(9));
+* optional prior terms of eq. (4) (Ornstein-Uhlenbeck, Sec. 4.1.2) through
+  ``pat_ou_prior``, added to J and to the gradient;
 * step: eq. (10) ``x <- P(x - alpha H g)`` with ``pat_lbfgs_direction``
   (Alg. 1, memory l) and ``pat_project_update`` (eq. (11)), backtracking
   (Armijo) line search with trial forward solves only;
@@ -45,7 +47,7 @@ class Problem:
     """One grid level: K datasets, observed traces y, weights w, bounds."""
 
     def __init__(self, wl: I.Workload, y: torch.Tensor, w: torch.Tensor, c_lo: float, c_hi: float,
-                 c_fixed: float = 1500.0, ckpt_every: int = 0, device="cuda"):
+                 c_fixed: float = 1500.0, ckpt_every: int = 0, device="cuda", prior: Optional[Dict] = None):
         self.wl = wl
         g = wl.grid
         self.plan = pat.Plan(g, wl.K, wl.sensors)
@@ -84,6 +86,19 @@ class Problem:
         self.dot_scratch = torch.empty(pat.lbfgs_scratch_bytes(0), dtype=torch.uint8, device=device)
         self.dot_out = torch.zeros(1, dtype=torch.float64, device=device)
         self.evals = 0
+        # eq. (4) prior terms (Ornstein-Uhlenbeck, Sec. 4.1.2): one operator over the
+        # reconstruction domain, a mean and a standard deviation per distribution
+        self.ou = None
+        if prior is not None:
+            self.ou = pat.OuPrior(g.ny, g.nx, g.dx, prior["tau"], mask.cpu().numpy())
+            eta = [prior["eta_p0"]] * self.K + [prior["eta_c"]]
+            sig = [prior["sigma_p0"]] * self.K + [prior["sigma_c"]]
+            self.eta = torch.tensor(eta, dtype=torch.float32, device=device)
+            self.inv_var = torch.tensor([1.0 / s_ ** 2 for s_ in sig], dtype=torch.float32, device=device)
+            self.g_prior = torch.empty((self.K + 1, g.ny, g.nx), dtype=torch.float32, device=device)
+            self.J_prior = torch.zeros(1, dtype=torch.float64, device=device)
+            self.prior_tol = prior.get("tol", 1e-6)
+            self.cg_iters = []
 
     def split(self, x: torch.Tensor):
         """Physical (p0 [K][ny][nx], c [ny][nx]) views of a physical stacked vector."""
@@ -91,19 +106,29 @@ class Problem:
         return x[: self.K * self.N].view(self.K, g.ny, g.nx), x[self.K * self.N:].view(g.ny, g.nx)
 
     def objective(self, z: torch.Tensor) -> float:
-        """J at scaled point z (recorded forward solve + misfit)."""
+        """J at scaled point z (recorded forward solve + misfit, plus the prior
+        terms when configured)."""
         self.x = z * self.scale            # kept alive: the adjoint reuses these buffers
         p0, c = self.split(self.x)
         self.plan.forward(c, p0, self.data, self.ws, ckpt_every=self.ckpt, record=True)
         self.plan.misfit(self.data, self.y, self.w, self.resid, self.J)
         self.evals += 1
-        return float(self.J.item())
+        J = float(self.J.item())
+        if self.ou is not None:
+            g = self.wl.grid
+            self.cg_iters.append(self.ou.prior(self.x.view(self.K + 1, g.ny, g.nx), self.eta, self.inv_var,
+                                               self.g_prior, self.J_prior, tol=self.prior_tol))
+            J += float(self.J_prior.item())
+        return J
 
     def gradient(self) -> torch.Tensor:
         """Scaled gradient at the point of the last ``objective`` call."""
         p0, c = self.split(self.x)
         self.plan.adjoint_gradient(c, p0, self.resid, self.gp0, self.gc, self.ws)
-        return torch.cat([self.gp0.reshape(-1), self.gc.reshape(-1)]) * self.scale
+        g = torch.cat([self.gp0.reshape(-1), self.gc.reshape(-1)])
+        if self.ou is not None:
+            g = g + self.g_prior.reshape(-1)
+        return g * self.scale
 
     def dot(self, a, b) -> float:
         pat.dot(a, b, self.dot_out, self.dot_scratch)
@@ -111,6 +136,8 @@ class Problem:
 
     def close(self):
         self.plan.close()
+        if self.ou is not None:
+            self.ou.close()
 
 
 def projected_lbfgs(prob: Problem, z0: torch.Tensor, iters: int, memory: int = 20, c1: float = 1e-4,
@@ -185,14 +212,16 @@ def relative_error_c(prob: Problem, z: torch.Tensor, c_true: torch.Tensor) -> fl
 def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w: torch.Tensor, c_true_fine,
               c_lo: float = 1400.0, c_hi: float = 1600.0, iters: int = 40, memory: int = 20,
               ckpt_every: int = 0, target_Ec: Optional[float] = None, log: Optional[Callable] = None,
-              c_init: Optional[float] = None, c_fixed: float = 1500.0):
+              c_init: Optional[float] = None, c_fixed: float = 1500.0, prior: Optional[Dict] = None):
     """Coarse-to-fine reconstruction (Sec. 3.1).  ``c_true_fine`` only measures
     E_c and never enters the optimisation: a tensor on the finest grid
     (resampled to coarser levels), or a callable ``level workload -> tensor``.
     Levels may differ in physical extent (Table 1); the converged iterate is
     carried to the next level at the same physical positions.  ``c_init``: the
     starting sound speed inside the mask (default: the middle of the bounds);
-    ``c_fixed``: the sound speed held outside the mask."""
+    ``c_fixed``: the sound speed held outside the mask.  ``prior``: the
+    Ornstein-Uhlenbeck prior terms of eq. (4) (keys tau, eta_p0, sigma_p0,
+    eta_c, sigma_c, optional tol), or None for bounds only."""
     device = y_fine.device
     results: List[LevelResult] = []
     z_prev = None
@@ -202,7 +231,7 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
         g = wl.grid
         y = torch.empty((wl.K, g.nt, wl.m), dtype=torch.float32, device=device)
         pat.time_interp(y_fine, dt_fine, y, g.dt)
-        prob = Problem(wl, y, w, c_lo, c_hi, c_fixed=c_fixed, ckpt_every=ckpt_every)
+        prob = Problem(wl, y, w, c_lo, c_hi, c_fixed=c_fixed, ckpt_every=ckpt_every, prior=prior)
         if z_prev is None:
             x0 = torch.empty(prob.n, dtype=torch.float32, device=device)
             x0[: prob.K * prob.N] = 0.0

@@ -57,3 +57,10 @@ def test_host_side_argument_checks():
     assert L.pat_batch_gradient(1, dummy, 17, None) == pat.PAT_EINVAL
     assert L.pat_trace_start(0) == pat.PAT_EINVAL
     assert L.pat_plan_set_tile(None, 0) == pat.PAT_EINVAL
+    # prior operator: refused before any device allocation
+    oh = ctypes.c_void_p()
+    assert L.pat_ou_create(0, 8, 1e-4, 1e-3, None, ctypes.byref(oh)) == pat.PAT_EINVAL
+    assert L.pat_ou_create(8, 8, 1e-4, 0.0, None, ctypes.byref(oh)) == pat.PAT_EINVAL
+    empty = (ctypes.c_uint8 * 64)()
+    assert L.pat_ou_create(8, 8, 1e-4, 1e-3, empty, ctypes.byref(oh)) == pat.PAT_EINVAL   # empty mask
+    assert L.pat_ou_create(300, 300, 1e-4, 1e-3, None, ctypes.byref(oh)) == pat.PAT_EUNSUPPORTED   # L > 512
