@@ -19,6 +19,10 @@ Contents
              projected quasi-Newton step with backtracking (eq. (10)),
              multigrid prolongation (Sec. 3.1) and data time resampling
              (Sec. 4.1.2), relative error (eq. (12)).
+``unet``     the learned fine-level start of the sound speed (replacing the
+             Sec. 3.1 interpolation): 3x3 convolutions, ReLU, pooling,
+             upsampling, masked squared loss and Adam, forward and backward
+             written from their definitions.
 
 Parity pins: every function is checked by ``tests/test_oracle_*.py`` against
 closed forms, invariants or brute force (see the module docstrings).  The full
