@@ -44,6 +44,12 @@ Pins (tests/test_oracle_unet.py)
 * the whole network's gradient equals central finite differences of the loss
   (weights, biases and the input);
 * Adam's first step moves each parameter by ``lr g / (|g| + eps)``.
+
+With ``store=bf16_round`` the forward and backward round every tensor kept
+between layers to bfloat16 (the storage precision of the GPU layers), so that
+ReLU decisions are taken on the same values as there; the full-precision
+default is what the pins above check, and the gap between the two is the cost
+of bfloat16 storage.
 """
 from __future__ import annotations
 
@@ -149,44 +155,59 @@ def init_params(cin: int, base: int, seed: int) -> Dict[str, np.ndarray]:
     return p
 
 
-def unet_forward(p: Dict[str, np.ndarray], x: np.ndarray):
-    """Output ``r [B][H][W]`` and the cache of every layer output."""
+def _same(a: np.ndarray) -> np.ndarray:
+    return a
+
+
+def unet_forward(p: Dict[str, np.ndarray], x: np.ndarray, store=None):
+    """Output ``r [B][H][W]`` and the cache of every layer output.
+
+    ``store`` (optional) is applied to every tensor the network keeps between
+    layers (layer outputs, pooled maps), e.g. ``bf16_round`` to take every
+    stored value, and so every ReLU decision downstream, in the precision of
+    a bfloat16-storage implementation; the default keeps full precision."""
+    keep = store or _same
     cache = {"in0": x}
     h = x
     for l in range(LEVELS):
         if l > 0:
-            h = avgpool2(cache[f"e{l - 1}b"])
+            h = keep(avgpool2(cache[f"e{l - 1}b"]))
             cache[f"in{l}"] = h
-        a = relu(conv3x3(h, p[f"e{l}a.w"], p[f"e{l}a.b"]))
+        a = keep(relu(conv3x3(h, p[f"e{l}a.w"], p[f"e{l}a.b"])))
         cache[f"e{l}a"] = a
-        h = relu(conv3x3(a, p[f"e{l}b.w"], p[f"e{l}b.b"]))
+        h = keep(relu(conv3x3(a, p[f"e{l}b.w"], p[f"e{l}b.b"])))
         cache[f"e{l}b"] = h
     d = cache[f"e{LEVELS - 1}b"]
     for l in range(LEVELS - 2, -1, -1):
         cat = np.concatenate([cache[f"e{l}b"], upsample2(d)], axis=-1)
         cache[f"cat{l}"] = cat
-        a = relu(conv3x3(cat, p[f"d{l}a.w"], p[f"d{l}a.b"]))
+        a = keep(relu(conv3x3(cat, p[f"d{l}a.w"], p[f"d{l}a.b"])))
         cache[f"d{l}a"] = a
-        d = relu(conv3x3(a, p[f"d{l}b.w"], p[f"d{l}b.b"]))
+        d = keep(relu(conv3x3(a, p[f"d{l}b.w"], p[f"d{l}b.b"])))
         cache[f"d{l}b"] = d
     r = head(d, p["head.w"], float(p["head.b"][0]))
     return r, cache
 
 
-def unet_backward(p: Dict[str, np.ndarray], cache, dr: np.ndarray):
-    """Gradients of ``sum(dr * r)`` wrt every parameter and the input."""
+def unet_backward(p: Dict[str, np.ndarray], cache, dr: np.ndarray, store=None):
+    """Gradients of ``sum(dr * r)`` wrt every parameter and the input.
+
+    ``store`` as in ``unet_forward``, applied to every gradient tensor kept
+    between layers (the gradient wrt each layer output and each concatenation,
+    and the running sum of a skip connection's two contributions)."""
+    keep = store or _same
     g: Dict[str, np.ndarray] = {}
     dd, g["head.w"], hb = head_backward(cache["d0b"], p["head.w"], dr)
     g["head.b"] = np.array([hb])
     d_out = {}          # gradient wrt each layer output (post-activation)
-    d_out["d0b"] = dd
+    d_out["d0b"] = keep(dd)
     for l in range(LEVELS - 1):
         d_out[f"e{l}b"] = np.zeros_like(cache[f"e{l}b"])
 
     def conv_back(name, x_key):
         pre = relu_backward(cache[name], d_out[name])
         dx, g[name + ".w"], g[name + ".b"] = conv3x3_backward(cache[x_key], p[name + ".w"], pre)
-        return dx
+        return keep(dx)
 
     for l in range(LEVELS - 1):
         d_out[f"d{l}a"] = conv_back(f"d{l}b", f"d{l}a")
@@ -194,13 +215,13 @@ def unet_backward(p: Dict[str, np.ndarray], cache, dr: np.ndarray):
         C = cache[f"e{l}b"].shape[-1]
         d_out[f"e{l}b"] += dcat[..., :C]
         below = f"d{l + 1}b" if l + 1 < LEVELS - 1 else f"e{LEVELS - 1}b"
-        d_out[below] = upsample2_backward(dcat[..., C:])
+        d_out[below] = keep(upsample2_backward(dcat[..., C:]))
     for l in range(LEVELS - 1, -1, -1):
         d_out[f"e{l}a"] = conv_back(f"e{l}b", f"e{l}a")
         x_key = f"in{l}"
         dx = conv_back(f"e{l}a", x_key)
         if l > 0:
-            d_out[f"e{l - 1}b"] += avgpool2_backward(dx)
+            d_out[f"e{l - 1}b"] = keep(d_out[f"e{l - 1}b"] + avgpool2_backward(dx))
         else:
             g["input"] = dx
     return g

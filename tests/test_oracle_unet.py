@@ -136,3 +136,29 @@ def test_bf16_rounding():
     assert U.bf16_round(np.array([1.0 + 0.49 * one_ulp]))[0] == 1.0
     x = np.random.default_rng(7).standard_normal(1000)
     assert np.max(np.abs(U.bf16_round(x) - x) / np.abs(x)) <= 2.0 ** -8
+
+
+def test_storage_rounding_mode():
+    """``store`` is applied to every tensor kept between layers: with
+    bf16_round every cached value is a bfloat16 number, the identity reproduces
+    the full-precision run bit for bit, and the rounded run stays within a few
+    bfloat16 roundings of it."""
+    rng = np.random.default_rng(8)
+    p = U.init_params(8, 8, seed=9)
+    p["head.w"] = rng.standard_normal(8)
+    x = U.bf16_round(rng.standard_normal((2, 16, 16, 8)))
+    r0, c0 = U.unet_forward(p, x)
+    r1, c1 = U.unet_forward(p, x, store=lambda a: a)
+    assert np.array_equal(r0, r1)
+    rb, cb = U.unet_forward(p, x, store=U.bf16_round)
+    for k, v in cb.items():
+        assert np.array_equal(U.bf16_round(v), v), k
+    assert np.linalg.norm(rb - r0) / np.linalg.norm(r0) < 2e-2
+    dr = rng.standard_normal(r0.shape)
+    g0 = U.unet_backward(p, c0, dr)
+    g1 = U.unet_backward(p, c0, dr, store=lambda a: a)
+    assert all(np.array_equal(g0[k], g1[k]) for k in g0)
+    gb = U.unet_backward(p, cb, dr, store=U.bf16_round)
+    num = sum(np.sum((gb[k] - g0[k]) ** 2) for k in g0 if k != "input")
+    den = sum(np.sum(g0[k] ** 2) for k in g0 if k != "input")
+    assert np.sqrt(num / den) < 0.1
