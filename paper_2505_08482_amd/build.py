@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpat.so")
 ARCH = "gfx950"
+SOURCES = ("pat_api.hip", "nn_api.hip")
 
 
 def hipcc() -> str:
@@ -39,7 +40,7 @@ def flags():
 
 def build(verbose: bool = True) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + ["-o", tmp, os.path.join(CSRC, "pat_api.hip")]
+    cmd = [hipcc()] + flags() + ["-o", tmp] + [os.path.join(CSRC, f) for f in SOURCES]
     t0 = time.time()
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -1,0 +1,611 @@
+// nn_kernels.hpp — the learned fine-level start of the sound speed (a U-Net
+// proposing the starting c of the next multigrid level, Sec. 3.1) on gfx950.
+//
+// Activations are channels-last bfloat16, [pixels][ld] with the channel slice
+// at a pointer offset (concatenations are channel slices of one buffer, so no
+// copy kernel exists).  bfloat16 values are stored as uint16_t: the upper half
+// of a float32, rounded to nearest even.
+//
+// Dense contractions run on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation):
+//  * k_conv3x3: implicit GEMM  Y[p][o] = sum_k A[p][k] Wt[o][k], k = (tap, ci),
+//    A[p][(t,c)] = X[p + offset_t][c] (zero outside the image).  The same
+//    kernel is the data gradient of a convolution when given the flipped
+//    weights (k_flip) and the gradient of the layer above.
+//  * k_wgrad: dW[o][(t,c)] = sum_p dY[p][o] X[p + offset_t][c] with the pixel
+//    sum split over blocks (partials reduced in a fixed order, k_wgrad_reduce).
+// MFMA operand layout (16x16x32): lane l supplies row (l mod 16) of A and
+// column (l mod 16) of B, each with 8 consecutive k; the accumulator holds
+// D[4 (l / 16) + r][l mod 16], r = 0..3.  The k order inside a step only has
+// to agree between A and B.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pat {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ u16x8 load8(const uint16_t* p) { return *reinterpret_cast<const u16x8*>(p); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, zero padding, as implicit GEMM
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+  const uint16_t* x;     // [B*H*W][ldx] (channel slice of cin)
+  const uint16_t* w;     // [cout][9][cin]
+  const float* bias;     // [cout] or null
+  uint16_t* y;           // [B*H*W][ldy] (channel slice of cout)
+  const uint16_t* mask;  // [B*H*W][ldm] or null: zero where mask <= 0
+  int B, H, W, cin, cout, ldx, ldy, ldm;
+  int relu, accum;
+};
+
+// Block: 4 waves in a 2 x 2 arrangement; a wave owns WM x WN MFMA tiles
+// (16 pixels x 16 output channels each).  Block tile: 32 WM pixels x 32 WN
+// output channels.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int r = lane & 15, kg = lane >> 4;
+  const int64_t P = (int64_t)a.B * a.H * a.W;
+  const int64_t m0 = (int64_t)blockIdx.x * (32 * WM) + wm * (16 * WM);
+  const int n0 = blockIdx.y * (32 * WN) + wn * (16 * WN);
+  const int ktot = 9 * a.cin;
+
+  int pb[WM], py[WM], px[WM];
+  bool pv[WM];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    int64_t p = m0 + 16 * i + r;
+    pv[i] = p < P;
+    if (!pv[i]) p = 0;
+    px[i] = (int)(p % a.W);
+    const int64_t t = p / a.W;
+    py[i] = (int)(t % a.H);
+    pb[i] = (int)(t / a.H);
+  }
+  const uint16_t* wrow[WN];
+  bool cv[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int co = n0 + 16 * j + r;
+    cv[j] = co < a.cout;
+    wrow[j] = a.w + (size_t)(cv[j] ? co : 0) * ktot;
+  }
+  f32x4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (a.cin % 32 == 0) {
+    // a 32-wide k step never crosses a tap: walk taps, then channel chunks
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const uint16_t* src[WM];
+      bool ok[WM];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int yy = py[i] + dy, xx = px[i] + dx;
+        ok[i] = pv[i] && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        src[i] = a.x + ((int64_t)(pb[i] * a.H + (ok[i] ? yy : 0)) * a.W + (ok[i] ? xx : 0)) * a.ldx + 8 * kg;
+      }
+      const int kt = tap * a.cin + 8 * kg;
+      for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        bf16x8 A[WM], Bv[WN];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) A[i] = as_bf16x8(ok[i] ? load8(src[i] + c0) : zero8);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) Bv[j] = as_bf16x8(cv[j] ? load8(wrow[j] + kt + c0) : zero8);
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
+      }
+    }
+  } else {
+    // cin a multiple of 8: each lane's 8 consecutive k stay inside one tap
+    for (int kc = 0; kc < ktot; kc += 32) {
+      const int k = kc + 8 * kg;
+      const bool kv = k < ktot;
+      const int tap = kv ? k / a.cin : 0;
+      const int ci = k - tap * a.cin;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      bf16x8 A[WM], Bv[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int yy = py[i] + dy, xx = px[i] + dx;
+        const bool ok = kv && pv[i] && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        A[i] = as_bf16x8(ok ? load8(a.x + ((int64_t)(pb[i] * a.H + yy) * a.W + xx) * a.ldx + ci) : zero8);
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) Bv[j] = as_bf16x8(kv && cv[j] ? load8(wrow[j] + k) : zero8);
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
+    }
+  }
+
+  // epilogue: lane holds output channel n0 + 16 j + r of pixels m0 + 16 i + 4 kg + q
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int co = n0 + 16 * j + r;
+    if (co >= a.cout) continue;
+    const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t p = m0 + 16 * i + 4 * kg + q;
+        if (p >= P) continue;
+        float v = acc[i][j][q] + bias;
+        if (a.relu) v = fmaxf(v, 0.f);
+        uint16_t* dst = a.y + p * a.ldy + co;
+        if (a.accum) v += bf2f(*dst);
+        if (a.mask && !(bf2f(a.mask[p * a.ldm + co]) > 0.f)) v = 0.f;
+        *dst = f2bf(v);
+      }
+  }
+}
+
+// Weights of the transposed convolution: wt[ci][t][co] = w[co][8 - t][ci]
+// (tap 8 - t is the opposite offset).
+__global__ void k_flip(int cout, int cin, const uint16_t* __restrict__ w, uint16_t* __restrict__ wt) {
+  const int64_t n = (int64_t)cout * 9 * cin;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int co = (int)(e % cout);
+    const int t = (int)((e / cout) % 9);
+    const int ci = (int)(e / ((int64_t)cout * 9));
+    wt[e] = w[((int64_t)co * 9 + (8 - t)) * cin + ci];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: block = 64 output channels x 64 (tap, ci) columns, pixel
+// chunks of 64 staged (transposed) through LDS; grid.z splits the pixels.
+// ---------------------------------------------------------------------------
+struct WgradArgs {
+  const uint16_t* x;    // [P][ldx] layer input slice (cin)
+  const uint16_t* dy;   // [P][ldy] gradient wrt the pre-activation (cout)
+  float* part;          // [nsplit][cout][9 cin]
+  float* partb;         // [nsplit][cout]
+  int B, H, W, cin, cout, ldx, ldy;
+  int64_t chunks_per_split;
+};
+
+constexpr int WG_CHUNK = 64;
+constexpr int WG_PAD = WG_CHUNK + 8;   // LDS row length (elements): 144 B rows stay 16-B aligned
+
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[64][WG_PAD];   // [co][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[64][WG_PAD];   // [(tap, ci)][pixel]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int r = lane & 15, kg = lane >> 4;
+  const int ktot = 9 * a.cin;
+  const int n0 = blockIdx.x * 64, co0 = blockIdx.y * 64;
+  const int64_t P = (int64_t)a.B * a.H * a.W;
+  const int64_t nchunks = (P + WG_CHUNK - 1) / WG_CHUNK;
+  const int64_t c_begin = blockIdx.z * a.chunks_per_split;
+  const int64_t c_end = c_begin + a.chunks_per_split < nchunks ? c_begin + a.chunks_per_split : nchunks;
+  const bool bias_block = blockIdx.x == 0;
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+
+  for (int64_t c = c_begin; c < c_end; ++c) {
+    const int64_t pbase = c * WG_CHUNK;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int g = tid + 256 * s;       // 512 groups of 8 values per operand
+      const int pl = g >> 3, grp = g & 7;
+      const int64_t p = pbase + pl;
+      // dY: 8 output channels of one pixel
+      const int co = co0 + 8 * grp;
+      const u16x8 vd = (p < P && co < a.cout) ? load8(a.dy + p * a.ldy + co) : zero8;
+      // X: 8 input channels of one tap of one pixel
+      const int n = n0 + 8 * grp;
+      u16x8 vx = zero8;
+      if (p < P && n < ktot) {
+        const int tap = n / a.cin, ci = n - tap * a.cin;
+        const int xx0 = (int)(p % a.W);
+        const int64_t t = p / a.W;
+        const int yy0 = (int)(t % a.H);
+        const int b = (int)(t / a.H);
+        const int yy = yy0 + tap / 3 - 1, xx = xx0 + tap % 3 - 1;
+        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          vx = load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + ci);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        sA[8 * grp + e][pl] = vd[e];
+        sB[8 * grp + e][pl] = vx[e];
+      }
+    }
+    __syncthreads();
+    if (bias_block && tid < 64)
+      for (int q = 0; q < WG_CHUNK; ++q) bsum += bf2f(sA[tid][q]);
+#pragma unroll
+    for (int ks = 0; ks < WG_CHUNK / 32; ++ks) {
+      bf16x8 A[2], Bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        A[i] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sA[32 * wm + 16 * i + r][32 * ks + 8 * kg]));
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        Bv[j] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sB[32 * wn + 16 * j + r][32 * ks + 8 * kg]));
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  float* part = a.part + (int64_t)blockIdx.z * a.cout * ktot;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = n0 + 32 * wn + 16 * j + r;
+    if (n >= ktot) continue;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int co = co0 + 32 * wm + 16 * i + 4 * kg + q;
+        if (co < a.cout) part[(int64_t)co * ktot + n] = acc[i][j][q];
+      }
+  }
+  if (bias_block && tid < 64 && co0 + tid < a.cout) a.partb[(int64_t)blockIdx.z * a.cout + co0 + tid] = bsum;
+}
+
+// dw[e] = sum_s part[s][e] (e over cout * 9 cin), db[o] = sum_s partb[s][o]; fixed order.
+__global__ void k_wgrad_reduce(int nsplit, int64_t nw, int cout, const float* __restrict__ part,
+                               const float* __restrict__ partb, float* __restrict__ dw, float* __restrict__ db) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nw + cout;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    if (e < nw) {
+      for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * nw + e];
+      dw[e] = s;
+    } else if (db) {
+      const int o = (int)(e - nw);
+      for (int z = 0; z < nsplit; ++z) s += partb[(int64_t)z * cout + o];
+      db[o] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2x2 average pooling, nearest upsampling and their adjoints (8 channels per
+// thread; C and the leading dimensions are multiples of 8)
+// ---------------------------------------------------------------------------
+// y[b][i][j] = mean of x[b][2i..2i+1][2j..2j+1]; x is [B][H][W], y [B][H/2][W/2]
+__global__ void k_avgpool2(int B, int H, int W, int C, const uint16_t* __restrict__ x, int ldx,
+                           uint16_t* __restrict__ y, int ldy) {
+  const int Ho = H / 2, Wo = W / 2, G = C / 8;
+  const int64_t n = (int64_t)B * Ho * Wo * G;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(e % G);
+    const int64_t q = e / G;
+    const int j = (int)(q % Wo);
+    const int i = (int)((q / Wo) % Ho);
+    const int b = (int)(q / ((int64_t)Wo * Ho));
+    const int64_t p00 = ((int64_t)b * H + 2 * i) * W + 2 * j;
+    const u16x8 v0 = load8(x + p00 * ldx + 8 * g), v1 = load8(x + (p00 + 1) * ldx + 8 * g);
+    const u16x8 v2 = load8(x + (p00 + W) * ldx + 8 * g), v3 = load8(x + (p00 + W + 1) * ldx + 8 * g);
+    u16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = f2bf(0.25f * ((bf2f(v0[k]) + bf2f(v1[k])) + (bf2f(v2[k]) + bf2f(v3[k]))));
+    *reinterpret_cast<u16x8*>(y + q * ldy + 8 * g) = o;
+  }
+}
+
+// dx[b][i][j] (fine, [B][H][W]) = (acc ? dx : 0) + dy[b][i/2][j/2] / 4, zero where mask <= 0
+__global__ void k_avgpool2_bwd(int B, int H, int W, int C, const uint16_t* __restrict__ dy, int ldy,
+                               uint16_t* __restrict__ dx, int ldx, const uint16_t* __restrict__ mask, int ldm,
+                               int accum) {
+  const int G = C / 8;
+  const int64_t n = (int64_t)B * H * W * G;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(e % G);
+    const int64_t p = e / G;
+    const int j = (int)(p % W);
+    const int i = (int)((p / W) % H);
+    const int b = (int)(p / ((int64_t)W * H));
+    const int64_t pc = ((int64_t)b * (H / 2) + i / 2) * (W / 2) + j / 2;
+    const u16x8 d = load8(dy + pc * ldy + 8 * g);
+    uint16_t* dst = dx + p * ldx + 8 * g;
+    const u16x8 old = accum ? load8(dst) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    const u16x8 m = mask ? load8(mask + p * ldm + 8 * g) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    u16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float v = 0.25f * bf2f(d[k]) + (accum ? bf2f(old[k]) : 0.f);
+      if (mask && !(bf2f(m[k]) > 0.f)) v = 0.f;
+      o[k] = f2bf(v);
+    }
+    *reinterpret_cast<u16x8*>(dst) = o;
+  }
+}
+
+// y (fine [B][H][W]) = x[b][i/2][j/2]
+__global__ void k_upsample2(int B, int H, int W, int C, const uint16_t* __restrict__ x, int ldx,
+                            uint16_t* __restrict__ y, int ldy) {
+  const int G = C / 8;
+  const int64_t n = (int64_t)B * H * W * G;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(e % G);
+    const int64_t p = e / G;
+    const int j = (int)(p % W);
+    const int i = (int)((p / W) % H);
+    const int b = (int)(p / ((int64_t)W * H));
+    const int64_t pc = ((int64_t)b * (H / 2) + i / 2) * (W / 2) + j / 2;
+    *reinterpret_cast<u16x8*>(y + p * ldy + 8 * g) = load8(x + pc * ldx + 8 * g);
+  }
+}
+
+// dx (coarse [B][H/2][W/2]) = sum of the four fine dy, zero where mask <= 0
+__global__ void k_upsample2_bwd(int B, int H, int W, int C, const uint16_t* __restrict__ dy, int ldy,
+                                uint16_t* __restrict__ dx, int ldx, const uint16_t* __restrict__ mask, int ldm) {
+  const int Ho = H / 2, Wo = W / 2, G = C / 8;
+  const int64_t n = (int64_t)B * Ho * Wo * G;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(e % G);
+    const int64_t q = e / G;
+    const int j = (int)(q % Wo);
+    const int i = (int)((q / Wo) % Ho);
+    const int b = (int)(q / ((int64_t)Wo * Ho));
+    const int64_t p00 = ((int64_t)b * H + 2 * i) * W + 2 * j;
+    const u16x8 v0 = load8(dy + p00 * ldy + 8 * g), v1 = load8(dy + (p00 + 1) * ldy + 8 * g);
+    const u16x8 v2 = load8(dy + (p00 + W) * ldy + 8 * g), v3 = load8(dy + (p00 + W + 1) * ldy + 8 * g);
+    const u16x8 m = mask ? load8(mask + q * ldm + 8 * g) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    u16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float v = (bf2f(v0[k]) + bf2f(v1[k])) + (bf2f(v2[k]) + bf2f(v3[k]));
+      if (mask && !(bf2f(m[k]) > 0.f)) v = 0.f;
+      o[k] = f2bf(v);
+    }
+    *reinterpret_cast<u16x8*>(dx + q * ldx + 8 * g) = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1x1 output head, its gradients, the masked squared loss
+// ---------------------------------------------------------------------------
+// r[p] = b + sum_c w[c] x[p][c]
+__global__ void k_head(int64_t P, int C, const uint16_t* __restrict__ x, int ldx, const uint16_t* __restrict__ w,
+                       const float* __restrict__ b, float* __restrict__ r) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    float s = b[0];
+    for (int g = 0; g < C / 8; ++g) {
+      const u16x8 v = load8(x + p * ldx + 8 * g), wv = load8(w + 8 * g);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s = fmaf(bf2f(wv[k]), bf2f(v[k]), s);
+    }
+    r[p] = s;
+  }
+}
+
+// dx[p][c] = [x > 0] w[c] dr[p]  (the gradient wrt the pre-activation of the layer below)
+__global__ void k_head_bwd_dx(int64_t P, int C, const uint16_t* __restrict__ x, int ldx,
+                              const uint16_t* __restrict__ w, const float* __restrict__ dr, uint16_t* __restrict__ dx,
+                              int lddx) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    const float d = dr[p];
+    for (int g = 0; g < C / 8; ++g) {
+      const u16x8 v = load8(x + p * ldx + 8 * g), wv = load8(w + 8 * g);
+      u16x8 o;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) o[k] = f2bf(bf2f(v[k]) > 0.f ? bf2f(wv[k]) * d : 0.f);
+      *reinterpret_cast<u16x8*>(dx + p * lddx + 8 * g) = o;
+    }
+  }
+}
+
+// part[blk][c] = sum over the block's pixels of dr[p] x[p][c]; part[blk][C] = sum dr.
+// 256 threads, C divides 256: thread t owns channel t mod C and pixel lane t / C.
+constexpr int HEAD_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_head_wgrad(int64_t P, int C, const uint16_t* __restrict__ x, int ldx,
+                                                    const float* __restrict__ dr, float* __restrict__ part) {
+  __shared__ float sh[256];
+  __shared__ float shb[256];
+  const int t = threadIdx.x, c = t % C, lanes = 256 / C, pl = t / C;
+  const int64_t per = (P + gridDim.x - 1) / gridDim.x;
+  const int64_t p0 = blockIdx.x * per, p1 = p0 + per < P ? p0 + per : P;
+  float s = 0.f, sb = 0.f;
+  for (int64_t p = p0 + pl; p < p1; p += lanes) {
+    const float d = dr[p];
+    s = fmaf(d, bf2f(x[p * ldx + c]), s);
+    if (c == 0) sb += d;
+  }
+  sh[t] = s;
+  shb[t] = sb;
+  __syncthreads();
+  if (t < C) {
+    float tot = 0.f;
+    for (int l = 0; l < lanes; ++l) tot += sh[l * C + t];
+    part[(int64_t)blockIdx.x * (C + 1) + t] = tot;
+  }
+  if (t == 0) {
+    float tb = 0.f;
+    for (int l = 0; l < lanes; ++l) tb += shb[l * C];
+    part[(int64_t)blockIdx.x * (C + 1) + C] = tb;
+  }
+}
+
+__global__ void k_head_wgrad_final(int nblk, int C, const float* __restrict__ part, float* __restrict__ dw,
+                                   float* __restrict__ db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > C) return;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * (C + 1) + c];
+  if (c < C) dw[c] = s;
+  else db[0] = s;
+}
+
+// Masked squared loss over B images sharing one mask [HW]:
+// partials of sum m (r - t)^2 and of the mask count, then L and dr.
+constexpr int MSE_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_mse_partial(int64_t n, int64_t hw, const float* __restrict__ r,
+                                                     const float* __restrict__ t, const uint8_t* __restrict__ mask,
+                                                     double* __restrict__ part) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (mask[i % hw]) {
+      const double e = (double)r[i] - (double)t[i];
+      a += e * e;
+      c += 1.0;
+    }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      s1[threadIdx.x] += s1[threadIdx.x + s];
+      s2[threadIdx.x] += s2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+// out[0] = L = sse / (2 count), out[1] = count
+__global__ void k_mse_final(int nblk, const double* __restrict__ part, double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double a = 0.0, c = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    a += part[2 * b];
+    c += part[2 * b + 1];
+  }
+  out[0] = c > 0.0 ? 0.5 * a / c : 0.0;
+  out[1] = c;
+}
+
+__global__ void k_mse_grad(int64_t n, int64_t hw, const float* __restrict__ r, const float* __restrict__ t,
+                           const uint8_t* __restrict__ mask, const double* __restrict__ stats,
+                           float* __restrict__ dr) {
+  const float inv = stats[1] > 0.0 ? (float)(1.0 / stats[1]) : 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dr[i] = mask[i % hw] ? (r[i] - t[i]) * inv : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Adam (bias-corrected), FP32 master weights, bf16 copy for the kernels
+// ---------------------------------------------------------------------------
+__global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ wb, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = f2bf(wi);
+  }
+}
+
+__global__ void k_to_bf16(int64_t n, const float* __restrict__ a, uint16_t* __restrict__ b) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = f2bf(a[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Network input: channel 0 = (c - shift) / scale, channel 1 = (sum_k g_k) /
+// max |sum_k g_k|, channels 2..7 = 0; optionally under one of the 8
+// symmetries of the square (bit 2: transpose, bit 0: flip rows, bit 1: flip
+// columns, applied to the output pixel to find its source pixel).
+// ---------------------------------------------------------------------------
+constexpr int PACK_BLOCKS = 256;
+
+__device__ __forceinline__ int64_t sym_src(int sym, int H, int W, int i, int j) {
+  if (sym & 1) i = H - 1 - i;
+  if (sym & 2) j = W - 1 - j;
+  if (sym & 4) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
+  return (int64_t)i * W + j;
+}
+
+__global__ __launch_bounds__(256) void k_gsum_absmax(int64_t hw, int K, const float* __restrict__ g,
+                                                     float* __restrict__ part) {
+  __shared__ float sh[256];
+  float mx = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hw; i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < K; ++k) s += g[(int64_t)k * hw + i];
+    mx = fmaxf(mx, fabsf(s));
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_pack_input(int H, int W, int K, const float* __restrict__ c_up, const float* __restrict__ g_up,
+                             const float* __restrict__ c_true, int sym, float shift, float inv_scale,
+                             const float* __restrict__ gpart, int npart, uint16_t* __restrict__ x,
+                             float* __restrict__ base, float* __restrict__ target) {
+  __shared__ float gscale;
+  if (threadIdx.x == 0) {
+    float mx = 0.f;
+    for (int b = 0; b < npart; ++b) mx = fmaxf(mx, gpart[b]);
+    gscale = mx > 0.f ? 1.f / mx : 0.f;
+  }
+  __syncthreads();
+  const int64_t hw = (int64_t)H * W;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < hw; p += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(p / W), j = (int)(p % W);
+    const int64_t s = sym_src(sym, H, W, i, j);
+    float gs = 0.f;
+    for (int k = 0; k < K; ++k) gs += g_up[(int64_t)k * hw + s];
+    const float c = c_up[s];
+    u16x8 o = {0, 0, 0, 0, 0, 0, 0, 0};
+    o[0] = f2bf((c - shift) * inv_scale);
+    o[1] = f2bf(gs * gscale);
+    *reinterpret_cast<u16x8*>(x + p * 8) = o;
+    base[p] = c;
+    if (target) target[p] = (c_true[s] - c) * inv_scale;
+  }
+}
+
+}  // namespace nn
+}  // namespace pat

@@ -1,0 +1,607 @@
+"""Learned fine-level start of the sound speed (replacing the linear
+interpolation of the coarse iterate that starts a finer multigrid level,
+Sec. 3.1), trained on the GPU by the library's own layer kernels.
+
+The network (a U-Net with 4 resolutions, ``base`` = 32 channels at the top,
+3x3 convolutions, ReLU, 2x2 average pooling, nearest upsampling, skip
+connections, a 1x1 head) reads the interpolated coarse sound speed and the
+interpolated sum over datasets of the initial-pressure gradient, and proposes
+a correction added to the interpolated sound speed; the result is projected
+onto the bounds of eq. (11).  Plain gradient iterations continue from it, so
+the reconstruction still decides the final c and remains the fallback.
+
+Every layer runs in ``libpat.so`` (``include/pat_nn.h``); this module owns the
+parameter layout, the buffers and the order of the layer calls.  Weights are
+bfloat16 for the kernels with float32 master copies for Adam.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import nn, pat
+
+LEVELS = 4
+CIN = 8            # input channels: (c, gradient sum, 6 zero channels)
+C_SHIFT = 1500.0   # m/s: input channel 0 is (c - C_SHIFT) / C_SCALE
+C_SCALE = 100.0    # m/s: the output is a correction in units of C_SCALE
+
+
+def layer_table(cin: int, base: int) -> List[Tuple[str, int, int]]:
+    """``(name, C_in, C_out)`` of the 3x3 convolutions in forward order:
+    encoder ``e{l}a, e{l}b`` (l = 0..3), decoder ``d{l}a, d{l}b`` (l = 2, 1, 0);
+    decoder inputs are ``[skip, upsampled]`` concatenations."""
+    ch = [base << l for l in range(LEVELS)]
+    table = []
+    c = cin
+    for l in range(LEVELS):
+        table.append((f"e{l}a", c, ch[l]))
+        table.append((f"e{l}b", ch[l], ch[l]))
+        c = ch[l]
+    for l in range(LEVELS - 2, -1, -1):
+        table.append((f"d{l}a", ch[l] + ch[l + 1], ch[l]))
+        table.append((f"d{l}b", ch[l], ch[l]))
+    return table
+
+
+class UNet:
+    """Parameters in one flat float32 buffer (per layer: weights [cout][9][cin],
+    then biases; the head's weights [base] and bias last), its bfloat16 copy,
+    gradients and Adam moments of the same layout."""
+
+    def __init__(self, base: int = 32, cin: int = CIN, seed: int = 0, device: str = "cuda"):
+        if cin % 8 or base % 8:
+            raise ValueError("channel counts must be multiples of 8")
+        self.base, self.cin, self.device = base, cin, device
+        self.table = layer_table(cin, base)
+        self.shapes = {name: (ci, co) for name, ci, co in self.table}
+        self.offsets: Dict[str, Tuple[int, int, int]] = {}
+        off = 0
+        for name, ci, co in self.table:
+            self.offsets[name] = (off, off + co * 9 * ci, co)
+            off += co * 9 * ci + co
+        self.head_off = off
+        self.n = off + base + 1
+        rng = np.random.default_rng(seed)
+        w = np.zeros(self.n, dtype=np.float32)
+        for name, ci, co in self.table:
+            o, ob, _ = self.offsets[name]
+            w[o:ob] = rng.standard_normal(co * 9 * ci) * np.sqrt(2.0 / (9 * ci))   # He-normal
+        self.w32 = torch.from_numpy(w).to(device)
+        self.wbf = torch.empty(self.n, dtype=torch.bfloat16, device=device)
+        self.grad = torch.zeros(self.n, dtype=torch.float32, device=device)
+        self.m = torch.zeros_like(self.grad)
+        self.v = torch.zeros_like(self.grad)
+        self.step = 0
+        self.sync_bf16()
+        self._bufs: Dict[Tuple[int, int, int], Dict] = {}
+        self._flip: Dict[str, torch.Tensor] = {}
+
+    # -- parameter views ----------------------------------------------------
+    def sync_bf16(self) -> None:
+        nn.to_bf16(self.w32, self.wbf)
+
+    def weight(self, name: str) -> torch.Tensor:
+        o, ob, co = self.offsets[name]
+        ci = self.shapes[name][0]
+        return self.wbf[o:ob].view(co, 9, ci)
+
+    def bias(self, name: str) -> torch.Tensor:
+        _, ob, co = self.offsets[name]
+        return self.w32[ob:ob + co]
+
+    def grad_views(self, name: str):
+        o, ob, co = self.offsets[name]
+        return self.grad[o:ob], self.grad[ob:ob + co]
+
+    def head_w(self) -> torch.Tensor:
+        return self.wbf[self.head_off:self.head_off + self.base]
+
+    def head_b(self) -> torch.Tensor:
+        return self.w32[self.head_off + self.base:self.head_off + self.base + 1]
+
+    def state(self) -> Dict[str, np.ndarray]:
+        """Float32 master parameters by name (``<layer>.w``, ``<layer>.b``, ``head.w``, ``head.b``)."""
+        w = self.w32.cpu().numpy()
+        out = {}
+        for name, ci, co in self.table:
+            o, ob, _ = self.offsets[name]
+            out[name + ".w"] = w[o:ob].reshape(co, 9, ci).copy()
+            out[name + ".b"] = w[ob:ob + co].copy()
+        out["head.w"] = w[self.head_off:self.head_off + self.base].copy()
+        out["head.b"] = w[self.head_off + self.base:].copy()
+        return out
+
+    def load(self, state: Dict[str, np.ndarray]) -> None:
+        w = np.zeros(self.n, dtype=np.float32)
+        for name, ci, co in self.table:
+            o, ob, _ = self.offsets[name]
+            w[o:ob] = np.asarray(state[name + ".w"], dtype=np.float32).reshape(-1)
+            w[ob:ob + co] = np.asarray(state[name + ".b"], dtype=np.float32).reshape(-1)
+        w[self.head_off:self.head_off + self.base] = np.asarray(state["head.w"], dtype=np.float32).reshape(-1)
+        w[self.head_off + self.base:] = np.asarray(state["head.b"], dtype=np.float32).reshape(-1)
+        self.w32.copy_(torch.from_numpy(w))
+        self.sync_bf16()
+
+    # -- buffers --------------------------------------------------------------
+    def buffers(self, B: int, H: int, W: int) -> Dict:
+        key = (B, H, W)
+        if key in self._bufs:
+            return self._bufs[key]
+        if H % (1 << (LEVELS - 1)) or W % (1 << (LEVELS - 1)):
+            raise ValueError(f"H and W must be multiples of {1 << (LEVELS - 1)}")
+        dev, bf = self.device, torch.bfloat16
+        ch = [self.base << l for l in range(LEVELS)]
+        res = [(H >> l, W >> l) for l in range(LEVELS)]
+
+        def act(l, c):
+            return torch.empty((B, res[l][0], res[l][1], c), dtype=bf, device=dev)
+
+        b: Dict = {"act": {}, "grad": {}}
+        A, G = b["act"], b["grad"]
+        for l in range(LEVELS):
+            if l > 0:
+                A[f"in{l}"] = act(l, ch[l - 1])
+                G[f"in{l}"] = act(l, ch[l - 1])
+            A[f"e{l}a"] = act(l, ch[l])
+            G[f"e{l}a"] = act(l, ch[l])
+        for l in range(LEVELS - 1):
+            A[f"cat{l}"] = act(l, ch[l] + ch[l + 1])
+            G[f"cat{l}"] = act(l, ch[l] + ch[l + 1])
+            A[f"e{l}b"] = A[f"cat{l}"][..., :ch[l]]          # skip half of the concatenation
+            G[f"e{l}b"] = G[f"cat{l}"][..., :ch[l]]
+            A[f"d{l}a"] = act(l, ch[l])
+            G[f"d{l}a"] = act(l, ch[l])
+            A[f"d{l}b"] = act(l, ch[l])
+            G[f"d{l}b"] = act(l, ch[l])
+        A[f"e{LEVELS - 1}b"] = act(LEVELS - 1, ch[LEVELS - 1])
+        G[f"e{LEVELS - 1}b"] = act(LEVELS - 1, ch[LEVELS - 1])
+        b["r"] = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+        scratch = max(nn.wgrad_scratch_bytes(B, res[int(name[1])][0], res[int(name[1])][1], ci, co)
+                      for name, ci, co in self.table)
+        b["scratch"] = torch.empty(max(scratch, nn.head_scratch_bytes(self.base)), dtype=torch.uint8, device=dev)
+        b["ch"] = ch
+        self._bufs[key] = b
+        return b
+
+    def flipped(self, name: str) -> torch.Tensor:
+        ci, co = self.shapes[name]
+        if name not in self._flip:
+            self._flip[name] = torch.empty((ci, 9, co), dtype=torch.bfloat16, device=self.device)
+        nn.conv3x3_flip(self.weight(name), self._flip[name])
+        return self._flip[name]
+
+    # -- forward / backward -----------------------------------------------------
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """``x [B][H][W][cin]`` bf16 -> ``r [B][H][W]`` float32 (a buffer of the net)."""
+        B, H, W, C = x.shape
+        if C != self.cin:
+            raise ValueError(f"expected {self.cin} input channels")
+        b = self.buffers(B, H, W)
+        A = b["act"]
+        self._x = x
+        h = x
+        for l in range(LEVELS):
+            if l > 0:
+                nn.avgpool2(A[f"e{l - 1}b"], A[f"in{l}"])
+                h = A[f"in{l}"]
+            nn.conv3x3(h, self.weight(f"e{l}a"), self.bias(f"e{l}a"), A[f"e{l}a"], relu=True)
+            nn.conv3x3(A[f"e{l}a"], self.weight(f"e{l}b"), self.bias(f"e{l}b"), A[f"e{l}b"], relu=True)
+        d = A[f"e{LEVELS - 1}b"]
+        ch = b["ch"]
+        for l in range(LEVELS - 2, -1, -1):
+            nn.upsample2(d, A[f"cat{l}"][..., ch[l]:])
+            nn.conv3x3(A[f"cat{l}"], self.weight(f"d{l}a"), self.bias(f"d{l}a"), A[f"d{l}a"], relu=True)
+            nn.conv3x3(A[f"d{l}a"], self.weight(f"d{l}b"), self.bias(f"d{l}b"), A[f"d{l}b"], relu=True)
+            d = A[f"d{l}b"]
+        nn.head(d, self.head_w(), self.head_b(), b["r"])
+        self._key = (B, H, W)
+        return b["r"]
+
+    def _layer_backward(self, b, name: str, x, dy, dx, mask) -> None:
+        """Weight / bias gradients of layer ``name`` (input x, pre-activation
+        gradient dy) and, if dx is given, the data gradient (masked by the
+        ReLU output that fed the layer, if any)."""
+        gw, gb = self.grad_views(name)
+        nn.conv3x3_wgrad(x, dy, gw, gb, b["scratch"])
+        if dx is not None:
+            nn.conv3x3(dy, self.flipped(name), None, dx, mask=mask)
+
+    def backward(self, dr: torch.Tensor) -> None:
+        """Gradients of ``sum(dr * r)`` for the last forward into ``self.grad``."""
+        b = self._bufs[self._key]
+        A, G, ch = b["act"], b["grad"], b["ch"]
+        hw = self.grad[self.head_off:self.head_off + self.base]
+        hb = self.grad[self.head_off + self.base:self.head_off + self.base + 1]
+        nn.head_backward(A["d0b"], self.head_w(), dr.contiguous(), G["d0b"], hw, hb, b["scratch"])
+        for l in range(LEVELS - 1):
+            self._layer_backward(b, f"d{l}b", A[f"d{l}a"], G[f"d{l}b"], G[f"d{l}a"], A[f"d{l}a"])
+            self._layer_backward(b, f"d{l}a", A[f"cat{l}"], G[f"d{l}a"], G[f"cat{l}"], A[f"cat{l}"])
+            below = f"d{l + 1}b" if l + 1 < LEVELS - 1 else f"e{LEVELS - 1}b"
+            nn.upsample2_backward(G[f"cat{l}"][..., ch[l]:], G[below], mask=A[below])
+        for l in range(LEVELS - 1, -1, -1):
+            self._layer_backward(b, f"e{l}b", A[f"e{l}a"], G[f"e{l}b"], G[f"e{l}a"], A[f"e{l}a"])
+            if l > 0:
+                self._layer_backward(b, f"e{l}a", A[f"in{l}"], G[f"e{l}a"], G[f"in{l}"], None)
+                nn.avgpool2_backward(G[f"in{l}"], G[f"e{l - 1}b"], mask=A[f"e{l - 1}b"], accumulate=True)
+            else:
+                self._layer_backward(b, "e0a", self._x, G["e0a"], None, None)
+
+    def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8) -> None:
+        self.step += 1
+        nn.adam(self.w32, self.grad, self.m, self.v, self.wbf, self.step, lr, b1, b2, eps)
+
+
+# ---------------------------------------------------------------------------
+# Training pairs generated by the method itself
+# ---------------------------------------------------------------------------
+COARSE_N, FINE_N = 128, 512
+
+
+def pair_phantoms(wl: I.Workload, j: int):
+    """Training phantom j: the 256^2 workload's generators (random-field c
+    with ellipses, vessel p0) at the workload's size, seeded by (5, 1, j, ...)
+    so that no training seed equals a held-out one."""
+    n = wl.grid.nx
+    c = I.grf_c(n, np.random.default_rng([5, 1, j]), wl.support_radius_px, corr_px=20.0 * n / 256.0)
+    p0 = np.stack([I.vessel_p0(n, np.random.default_rng([5, 1, j, k + 1]), wl.support_radius_px)
+                   for k in range(wl.K)])
+    return c, p0
+
+
+def simulate(wl: I.Workload, c: np.ndarray, p0: np.ndarray, noise_seed) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Noisy sensor data (1 % of each dataset's peak-to-peak) and weights 1/sigma."""
+    plan = pat.Plan(wl.grid, wl.K, wl.sensors)
+    try:
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+        data = torch.empty(plan.data_shape, dtype=torch.float32, device="cuda")
+        ws = plan.workspace(0)
+        plan.forward(T(c), T(p0), data, ws, record=False)
+        clean = data.cpu().numpy().astype(np.float64)
+        del ws
+    finally:
+        plan.close()
+    noisy, sigma = I.add_noise(clean, noise_seed)
+    return (torch.from_numpy(noisy.astype(np.float32)).cuda(),
+            torch.from_numpy((1.0 / sigma).astype(np.float32)).cuda())
+
+
+@dataclasses.dataclass
+class CoarseResult:
+    c: torch.Tensor          # [n][n] sound speed of the coarse level
+    p0: torch.Tensor         # [K][n][n]
+    g_p0: torch.Tensor       # [K][n][n] gradient of J wrt p0 at the final iterate
+    iters: int
+    seconds: float
+    dx: float
+
+
+def coarse_level(y_fine: torch.Tensor, dt_fine: float, w: torch.Tensor, K: int, iters: int = 40,
+                 n: int = COARSE_N, c_lo: float = 1400.0, c_hi: float = 1600.0) -> CoarseResult:
+    """The coarsest multigrid level of Sec. 3.1 (projected L-BFGS from c = the
+    middle of the bounds, p0 = 0), returning its iterate and p0 gradient."""
+    from . import recon
+    t0 = time.perf_counter()
+    wl = I.config3_level(n, K=K)
+    g = wl.grid
+    y = torch.empty((K, g.nt, wl.m), dtype=torch.float32, device="cuda")
+    pat.time_interp(y_fine, dt_fine, y, g.dt)
+    prob = recon.Problem(wl, y, w, c_lo, c_hi)
+    try:
+        x0 = torch.zeros(prob.n, dtype=torch.float32, device="cuda")
+        x0[prob.K * prob.N:] = 0.5 * (c_lo + c_hi)
+        z, J, hist, nit = recon.projected_lbfgs(prob, x0 / prob.scale, iters)
+        p0, c = prob.split(z * prob.scale)
+        out = CoarseResult(c.clone(), p0.clone(), prob.gp0.clone(), nit, 0.0, g.dx)
+        torch.cuda.synchronize()
+        out.seconds = time.perf_counter() - t0
+    finally:
+        prob.close()
+    return out
+
+
+def fine_inputs(coarse: CoarseResult, fine: I.Workload) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Interpolated coarse c [H][W] and p0 gradients [K][H][W] on the fine grid
+    (same physical positions, Sec. 3.1)."""
+    g = fine.grid
+    K = coarse.p0.shape[0]
+    src = torch.cat([coarse.c.reshape(1, *coarse.c.shape), coarse.g_p0]).contiguous()
+    out = torch.empty((K + 1, g.ny, g.nx), dtype=torch.float32, device="cuda")
+    pat.prolong_phys(src, coarse.dx, out, g.dx)
+    return out[0], out[1:]
+
+
+class LearnedStart:
+    """Inference: the fine-level starting sound speed proposed by the network."""
+
+    def __init__(self, net: UNet, fine: I.Workload, c_lo: float = 1400.0, c_hi: float = 1600.0,
+                 c_fixed: float = 1500.0):
+        self.net, self.fine = net, fine
+        g = fine.grid
+        self.x = torch.empty((1, g.ny, g.nx, CIN), dtype=torch.bfloat16, device="cuda")
+        self.base = torch.empty((g.ny, g.nx), dtype=torch.float32, device="cuda")
+        self.scratch = torch.empty(nn.pack_scratch_bytes(), dtype=torch.uint8, device="cuda")
+        mask = torch.from_numpy(fine.mask().astype(np.bool_)).cuda()
+        self.lo = torch.where(mask, torch.tensor(c_lo, device="cuda"), torch.tensor(c_fixed, device="cuda")).reshape(-1)
+        self.hi = torch.where(mask, torch.tensor(c_hi, device="cuda"), torch.tensor(c_fixed, device="cuda")).reshape(-1)
+
+    def __call__(self, c_up: torch.Tensor, g_up: torch.Tensor) -> torch.Tensor:
+        nn.pack_input(c_up.contiguous(), g_up.contiguous(), None, 0, C_SHIFT, C_SCALE, self.x, self.base, None,
+                      self.scratch)
+        r = self.net.forward(self.x)
+        c = self.base.reshape(-1).clone()
+        pat.project_update(c, r.reshape(-1), -C_SCALE, self.lo, self.hi)   # c = P(base + scale r)
+        return c.view(self.fine.grid.ny, self.fine.grid.nx)
+
+
+def train(net: UNet, coarse_c: torch.Tensor, coarse_g: torch.Tensor, c_true: torch.Tensor, fine: I.Workload,
+          coarse_dx: float, epochs: int, batch: int = 4, lr: float = 1e-3, seed: int = 0, log=None,
+          symmetries: Sequence[int] = tuple(range(8)), time_budget: Optional[float] = None) -> List[float]:
+    """Adam on the masked squared error of the correction (in units of
+    C_SCALE) over pairs (coarse c [n][h][w], summed p0 gradient [n][h][w],
+    true fine c [n][H][W]); every pair is used under each symmetry of the
+    square in ``symmetries`` (the sensor ring and grids share them)."""
+    g = fine.grid
+    H, W = g.ny, g.nx
+    npairs = coarse_c.shape[0]
+    mask = torch.from_numpy(fine.mask().astype(np.uint8)).cuda()
+    X = torch.empty((batch, H, W, CIN), dtype=torch.bfloat16, device="cuda")
+    base = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
+    target = torch.empty_like(base)
+    up = torch.empty((2, H, W), dtype=torch.float32, device="cuda")
+    dr = torch.empty_like(base)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    pack_scratch = torch.empty(nn.pack_scratch_bytes(), dtype=torch.uint8, device="cuda")
+    mse_scratch = torch.empty(nn.mse_scratch_bytes(), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(seed)
+    items = [(j, s) for j in range(npairs) for s in symmetries]
+    losses = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        order = rng.permutation(len(items))
+        tot, cnt = 0.0, 0
+        for start in range(0, len(order) - batch + 1, batch):
+            for bi, it in enumerate(order[start:start + batch]):
+                j, s = items[it]
+                src = torch.stack([coarse_c[j], coarse_g[j]]).contiguous()
+                pat.prolong_phys(src, coarse_dx, up, g.dx)
+                nn.pack_input(up[0], up[1], c_true[j], s, C_SHIFT, C_SCALE, X[bi:bi + 1], base[bi], target[bi],
+                              pack_scratch)
+            r = net.forward(X)
+            nn.masked_mse(r, target, mask, dr, out, mse_scratch)
+            net.backward(dr)
+            net.adam(lr)
+            tot += float(out[0].item())
+            cnt += 1
+            if time_budget is not None and time.perf_counter() - t0 > time_budget:
+                break
+        losses.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep + 1}: loss {losses[-1]:.5f} ({time.perf_counter() - t0:.1f} s)")
+        if time_budget is not None and time.perf_counter() - t0 > time_budget:
+            break
+    return losses
+
+
+def save_weights(net: UNet, path: str) -> None:
+    st = net.state()
+    np.savez_compressed(path, base=np.array([net.base]), cin=np.array([net.cin]), **st)
+
+
+def load_weights(path: str, device: str = "cuda") -> UNet:
+    with np.load(path, allow_pickle=False) as f:
+        net = UNet(base=int(f["base"][0]), cin=int(f["cin"][0]), device=device)
+        net.load({k: f[k] for k in f.files if k not in ("base", "cin")})
+    return net
+
+
+# ---------------------------------------------------------------------------
+# Fine level from a given start; evaluation against plain multigrid
+# ---------------------------------------------------------------------------
+def relative_error(c: torch.Tensor, c_true: torch.Tensor, mask: torch.Tensor) -> float:
+    """Eq. (12) for c over the reconstruction mask, in percent."""
+    return 100.0 * float(torch.linalg.vector_norm((c - c_true)[mask]) / torch.linalg.vector_norm(c_true[mask]))
+
+
+def fine_level(fine: I.Workload, y_fine: torch.Tensor, w: torch.Tensor, c0: torch.Tensor, p00: torch.Tensor,
+               c_true: torch.Tensor, iters: int, target: Optional[float] = None, t_origin: Optional[float] = None,
+               c_lo: float = 1400.0, c_hi: float = 1600.0):
+    """Projected L-BFGS on the fine level from (p0 = p00, c = c0); E_c and wall
+    time (from ``t_origin``) after every iteration; stops once E_c <= target."""
+    from . import recon
+    t_origin = time.perf_counter() if t_origin is None else t_origin
+    prob = recon.Problem(fine, y_fine, w, c_lo, c_hi)
+    try:
+        x0 = torch.cat([p00.reshape(-1), c0.reshape(-1)]).contiguous()
+        z0 = x0 / prob.scale
+        pat.project_update(z0, torch.zeros_like(z0), 0.0, prob.lo_z, prob.hi_z)
+        mask = prob.mask
+        E = [relative_error(prob.split(z0 * prob.scale)[1], c_true, mask)]
+        T = [time.perf_counter() - t_origin]
+
+        def cb(it, z, J):
+            E.append(relative_error(prob.split(z * prob.scale)[1], c_true, mask))
+            T.append(time.perf_counter() - t_origin)
+            return target is not None and E[-1] <= target
+
+        if not (target is not None and E[0] <= target):
+            recon.projected_lbfgs(prob, z0, iters, callback=cb)
+        torch.cuda.synchronize()
+    finally:
+        prob.close()
+    return E, T
+
+
+def first_at(E: Sequence[float], T: Sequence[float], target: float):
+    for i, (e, t) in enumerate(zip(E, T)):
+        if e <= target:
+            return i, t
+    return None, None
+
+
+def evaluate_case(net: Optional[UNet], case: int, K: int = 8, coarse_iters: int = 40, fine_iters: int = 20,
+                  target: float = 2.0, plain_multigrid: bool = True, log=None) -> Dict:
+    """One held-out phantom (the 256^2 workload's generators at 512^2, seeds
+    5000 + case): plain multigrid 128 -> 256 -> 512 against the coarse level
+    followed directly by the fine level, started from the plain interpolation
+    of the coarse iterate and from the network's proposal."""
+    from . import recon
+    fine = I.config3_level(FINE_N, K=K)
+    c_np, p0_np = I.phantoms(fine, 5, case=case)
+    c_true = torch.from_numpy(c_np.astype(np.float32)).cuda()
+    y, w = simulate(fine, c_np, p0_np, noise_seed=5000 + case + 500)
+    dt = fine.grid.dt
+    mask = torch.from_numpy(fine.mask().astype(np.bool_)).cuda()
+    res: Dict = {"case": case}
+    # coarse level, shared by both starts
+    t0 = time.perf_counter()
+    co = coarse_level(y, dt, w, K, iters=coarse_iters)
+    c_up, g_up = fine_inputs(co, fine)
+    src = co.p0.contiguous()
+    p0_up = torch.empty((K, fine.grid.ny, fine.grid.nx), dtype=torch.float32, device="cuda")
+    pat.prolong_phys(src, co.dx, p0_up, fine.grid.dx)
+    t_coarse = time.perf_counter() - t0
+    res["coarse_seconds"] = round(t_coarse, 3)
+    starts = {"interpolated": c_up.clone()}
+    if net is not None:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        starts["learned"] = LearnedStart(net, fine)(c_up, g_up).clone()
+        torch.cuda.synchronize()
+        res["network_seconds"] = round(time.perf_counter() - t1, 4)
+    for name, c0 in starts.items():
+        t_start = time.perf_counter() - (t_coarse + (res.get("network_seconds", 0.0) if name == "learned" else 0.0))
+        E, T = fine_level(fine, y, w, c0, p0_up, c_true, fine_iters, target=target, t_origin=t_start)
+        i, t = first_at(E, T, target)
+        res[name] = {"E_c_start": round(E[0], 3), "E_c_last": round(E[-1], 3), "fine_iterations": len(E) - 1,
+                     "fine_iterations_to_target": i, "seconds_to_target": None if t is None else round(t, 2),
+                     "iterations_to_target": None if i is None else co.iters + i}
+        if log:
+            log(f"case {case} {name}: E_c start {E[0]:.3f} % -> {E[-1]:.3f} %, target at fine iteration {i} "
+                f"({'-' if t is None else f'{t:.2f} s'})")
+    if plain_multigrid:
+        levels = [I.config3_level(n, K=K) for n in (COARSE_N, 256, FINE_N)]
+        hit = {}
+
+        def cb(msg):
+            pass
+        t2 = time.perf_counter()
+        out = recon.multigrid(levels, y, dt, w, c_true, iters=coarse_iters, log=cb)
+        total = time.perf_counter() - t2
+        fl = out["levels"][-1]
+        its_before = sum(lv.iters for lv in out["levels"][:-1])
+        i, t = first_at(fl.E_c, fl.t, target)
+        if i is not None:
+            hit = {"iterations_to_target": its_before + i + 1, "seconds_to_target": round(fl.t_start + t, 2)}
+        res["plain_multigrid"] = {"E_c_fine_start": None, "E_c_last": round(out["E_c"], 3),
+                                  "seconds_total": round(total, 2), **hit}
+        if log:
+            log(f"case {case} plain multigrid: final E_c {out['E_c']:.3f} %, {hit or 'target not reached'}")
+    return res
+
+
+# ---------------------------------------------------------------------------
+# Command line: generate pairs, train, evaluate
+# ---------------------------------------------------------------------------
+def generate_pairs(start: int, count: int, K: int = 8, coarse_iters: int = 40, log=print) -> Dict[str, np.ndarray]:
+    fine = I.config3_level(FINE_N, K=K)
+    cs, gs, ecs, secs = [], [], [], []
+    for j in range(start, start + count):
+        t0 = time.perf_counter()
+        c_np, p0_np = pair_phantoms(fine, j)
+        y, w = simulate(fine, c_np, p0_np, noise_seed=[5, 1, j, 500])
+        co = coarse_level(y, fine.grid.dt, w, K, iters=coarse_iters)
+        cs.append(co.c.cpu().numpy())
+        gs.append(co.g_p0.sum(0).cpu().numpy())
+        c_up, _ = fine_inputs(co, fine)
+        m = torch.from_numpy(fine.mask().astype(np.bool_)).cuda()
+        ecs.append(relative_error(c_up, torch.from_numpy(c_np.astype(np.float32)).cuda(), m))
+        secs.append(time.perf_counter() - t0)
+        if log:
+            log(f"pair {j}: coarse iterations {co.iters}, interpolated E_c {ecs[-1]:.3f} %, {secs[-1]:.2f} s")
+    return {"index": np.arange(start, start + count), "c": np.stack(cs).astype(np.float32),
+            "gsum": np.stack(gs).astype(np.float32), "E_c_interp": np.array(ecs), "seconds": np.array(secs)}
+
+
+def truth_for_pairs(index: Sequence[int], K: int = 8) -> np.ndarray:
+    fine = I.config3_level(FINE_N, K=K)
+    return np.stack([pair_phantoms(fine, int(j))[0] for j in index]).astype(np.float32)
+
+
+def main(argv=None) -> int:
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("gen", help="generate training pairs with the plain method")
+    g.add_argument("--start", type=int, default=0)
+    g.add_argument("--count", type=int, default=8)
+    g.add_argument("--out", required=True)
+    t = sub.add_parser("train", help="train the network on generated pairs")
+    t.add_argument("--pairs", nargs="+", required=True)
+    t.add_argument("--epochs", type=int, default=10)
+    t.add_argument("--batch", type=int, default=4)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--minutes", type=float, default=None, help="stop after this much training time")
+    t.add_argument("--holdout", type=int, default=0, help="pairs kept out of training for a validation loss")
+    t.add_argument("--out", required=True)
+    e = sub.add_parser("eval", help="held-out phantoms: learned start vs plain multigrid")
+    e.add_argument("--weights", default=None)
+    e.add_argument("--cases", type=int, nargs="+", default=[0, 1])
+    e.add_argument("--fine-iters", type=int, default=20)
+    e.add_argument("--no-multigrid", action="store_true")
+    e.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)
+    if a.cmd == "gen":
+        d = generate_pairs(a.start, a.count, log=log)
+        np.savez(a.out, **d)
+        return 0
+    if a.cmd == "train":
+        parts = [np.load(p, allow_pickle=False) for p in a.pairs]
+        index = np.concatenate([p["index"] for p in parts])
+        cc = np.concatenate([p["c"] for p in parts])
+        gg = np.concatenate([p["gsum"] for p in parts])
+        ntr = len(index) - a.holdout
+        log(f"{len(index)} pairs ({ntr} for training), generating the true 512^2 sound speeds")
+        truth = truth_for_pairs(index)
+        fine = I.config3_level(FINE_N, K=8)
+        coarse_dx = I.config3_level(COARSE_N, K=8).grid.dx
+        T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        net = UNet(base=32, seed=0)
+        t0 = time.perf_counter()
+        losses = train(net, T(cc[:ntr]), T(gg[:ntr]), T(truth[:ntr]), fine, coarse_dx, a.epochs, batch=a.batch,
+                       lr=a.lr, log=log, time_budget=None if a.minutes is None else 60.0 * a.minutes)
+        torch.cuda.synchronize()
+        log(f"trained {net.step} steps in {time.perf_counter() - t0:.1f} s")
+        save_weights(net, a.out)
+        if a.holdout:
+            ls = LearnedStart(net, fine)
+            mask = torch.from_numpy(fine.mask().astype(np.bool_)).cuda()
+            e0, e1 = [], []
+            for j in range(ntr, len(index)):
+                c_up = torch.empty((2, fine.grid.ny, fine.grid.nx), dtype=torch.float32, device="cuda")
+                pat.prolong_phys(T(np.stack([cc[j], gg[j]])), coarse_dx, c_up, fine.grid.dx)
+                ct = T(truth[j])
+                e0.append(relative_error(c_up[0], ct, mask))
+                e1.append(relative_error(ls(c_up[0], c_up[1:2]), ct, mask))
+            log(f"held-out pairs: E_c interpolated {np.mean(e0):.3f} %, learned {np.mean(e1):.3f} %")
+        return 0
+    if a.cmd == "eval":
+        net = load_weights(a.weights) if a.weights else None
+        rows = [evaluate_case(net, c, fine_iters=a.fine_iters, plain_multigrid=not a.no_multigrid, log=log)
+                for c in a.cases]
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(rows, f, indent=1)
+        return 0
+    return 1
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -197,8 +197,8 @@ def projected_lbfgs(prob: Problem, z0: torch.Tensor, iters: int, memory: int = 2
                 S.pop(0); Y.pop(0)
         z, J, g = zt, Jt, gt
         hist.append(J)
-        if callback is not None:
-            callback(it, z, J)
+        if callback is not None and callback(it, z, J):
+            break            # the caller's stopping rule (e.g. a target error reached)
     return z, J, hist, it + 1
 
 

@@ -1,0 +1,349 @@
+"""GPU parity of the learned-start layers (include/pat_nn.h) and of the whole
+network against the FP64 oracle (oracle/unet.py) on the same bf16-rounded
+inputs.
+
+Tolerances follow from the arithmetic: products of bf16 operands are exact in
+float32, the float32 accumulation adds at most ~1e-5 of the sum of absolute
+terms S (computed by the oracle on |x|, |w|), and a bf16 result adds the
+rounding of 2^-9 relative (bound 2^-8 used).  Float32 outputs (weight
+gradients, head) carry the accumulation term only.  Through the whole network
+the bf16 storage of every activation and gradient compounds, and a ReLU
+decision flips wherever the two sides' stored values straddle zero; so the
+network is compared with the oracle run in the same storage precision
+(``store=bf16_round``: every kept tensor rounded to bf16), and the gap between
+that run and the full-precision one (the cost of bf16 storage) is reported
+beside it.  The bf16-storage network at random initialisation is sensitive to
+summation order: a value that lands on the other side of a bf16 rounding
+boundary moves by one unit, and such moves cascade through the layers
+(running the same oracle with float32 instead of float64 accumulation changes
+its 64 x 64, base-32 output by 7.0e-3 relative, the share of differing stored
+values growing from 2e-5 in the first layers to 29 % in the last).  The
+whole-network bars are therefore set at about three times that order
+sensitivity; the layer-level tests above carry the tight bounds.
+"""
+import numpy as np
+import pytest
+
+from oracle import unet as U
+from tests.gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_08482_amd import learned, nn  # noqa: E402
+
+BF16_REL = 2.0 ** -8
+ACC = 1e-5
+
+
+def bf(a):
+    """bf16 GPU tensor of a float array, and the float64 values it holds."""
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).cuda()
+    return t, t.float().cpu().numpy().astype(np.float64)
+
+
+def f32(a):
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    return t, t.cpu().numpy().astype(np.float64)
+
+
+def back(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def assert_close(got, ref, scale, rel=BF16_REL, acc=ACC, what=""):
+    err = np.abs(got - ref)
+    bound = rel * np.abs(ref) + acc * scale + 1e-30
+    bad = err > bound
+    assert not bad.any(), (what, int(bad.sum()), float(err[bad].max()), float(np.max(err / bound)))
+
+
+CONV_CASES = [
+    # B, H, W, cin, cout, x channel offset/ld, y channel offset/ld
+    (2, 13, 21, 8, 32, (0, 8), (0, 32)),        # generic k walk (cin 8), 128-pixel tiles, ragged tail
+    (2, 13, 21, 32, 64, (0, 32), (0, 64)),      # tap walk, 64 x 64 tiles
+    (1, 9, 30, 96, 96, (0, 96), (0, 96)),       # two output tiles, the second half full
+    (1, 16, 16, 64, 32, (16, 96), (32, 96)),    # channel slices of wider buffers
+    (3, 8, 8, 128, 256, (0, 128), (0, 256)),
+]
+
+
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv_forward_matches_oracle(case):
+    B, H, W, cin, cout, (xo, ldx), (yo, ldy) = case
+    announce(f"nn conv forward {case}")
+    rng = np.random.default_rng(10 + cin + cout)
+    xbuf, xbuf64 = bf(rng.standard_normal((B, H, W, ldx)))
+    x, x64 = xbuf[..., xo:xo + cin], xbuf64[..., xo:xo + cin]
+    w, w64 = bf(rng.standard_normal((cout, 9, cin)) / np.sqrt(9 * cin))
+    b, b64 = f32(0.1 * rng.standard_normal(cout))
+    ybuf = torch.full((B, H, W, ldy), 7.0, dtype=torch.bfloat16, device="cuda")
+    nn.conv3x3(x, w, b, ybuf[..., yo:yo + cout], relu=True)
+    torch.cuda.synchronize()
+    ref = U.relu(U.conv3x3(x64, w64, b64))
+    S = U.conv3x3(np.abs(x64), np.abs(w64), np.abs(b64))
+    got = back(ybuf)
+    assert_close(got[..., yo:yo + cout], ref, S, what="conv forward")
+    # channels outside the slice are untouched
+    outside = np.ones(ldy, dtype=bool)
+    outside[yo:yo + cout] = False
+    assert np.all(got[..., outside] == 7.0)
+
+
+@pytest.mark.parametrize("case", CONV_CASES[:4])
+def test_conv_data_gradient_matches_oracle(case):
+    """Flipped weights + mask (+ accumulate) give dx = [mask > 0] (old + A^T dy)."""
+    B, H, W, cin, cout, _, _ = case
+    announce(f"nn conv data gradient {case}")
+    rng = np.random.default_rng(20 + cin + cout)
+    w, w64 = bf(rng.standard_normal((cout, 9, cin)) / np.sqrt(9 * cin))
+    dy, dy64 = bf(rng.standard_normal((B, H, W, cout)))
+    mask, mask64 = bf(np.maximum(rng.standard_normal((B, H, W, cin)), 0.0))
+    wt = torch.empty((cin, 9, cout), dtype=torch.bfloat16, device="cuda")
+    nn.conv3x3_flip(w, wt)
+    dx = torch.empty((B, H, W, cin), dtype=torch.bfloat16, device="cuda")
+    nn.conv3x3(dy, wt, None, dx, mask=mask)
+    torch.cuda.synchronize()
+    ref, _, _ = U.conv3x3_backward(np.zeros((B, H, W, cin)), w64, dy64)
+    S, _, _ = U.conv3x3_backward(np.zeros((B, H, W, cin)), np.abs(w64), np.abs(dy64))
+    ref = ref * (mask64 > 0)
+    assert_close(back(dx), ref, S, what="data gradient")
+    assert np.array_equal(back(wt), np.transpose(w64[:, ::-1, :], (2, 1, 0)))
+    # accumulate into an existing gradient
+    old, old64 = bf(rng.standard_normal((B, H, W, cin)))
+    nn.conv3x3(dy, wt, None, old, accumulate=True, mask=mask)
+    torch.cuda.synchronize()
+    raw, _, _ = U.conv3x3_backward(np.zeros((B, H, W, cin)), w64, dy64)
+    assert_close(back(old), (old64 + raw) * (mask64 > 0), S + np.abs(old64), what="accumulate")
+
+
+WGRAD_CASES = [
+    (2, 40, 37, 32, 64, (0, 32), (0, 64)),      # 2960 pixels: 47 chunks, ragged last chunk
+    (1, 33, 31, 8, 32, (0, 8), (0, 32)),        # 72 (tap, ci) columns: two column tiles
+    (2, 16, 16, 96, 32, (0, 96), (0, 32)),
+    (1, 24, 24, 64, 128, (64, 192), (0, 128)),  # input is a slice of a concatenation
+]
+
+
+@pytest.mark.parametrize("case", WGRAD_CASES)
+def test_weight_gradient_matches_oracle(case):
+    B, H, W, cin, cout, (xo, ldx), (yo, ldy) = case
+    announce(f"nn weight gradient {case}")
+    rng = np.random.default_rng(30 + cin + cout)
+    xbuf, xbuf64 = bf(np.maximum(rng.standard_normal((B, H, W, ldx)), 0.0))
+    x, x64 = xbuf[..., xo:xo + cin], xbuf64[..., xo:xo + cin]
+    dybuf, dybuf64 = bf(rng.standard_normal((B, H, W, ldy)))
+    dy, dy64 = dybuf[..., yo:yo + cout], dybuf64[..., yo:yo + cout]
+    dw = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(nn.wgrad_scratch_bytes(B, H, W, cin, cout), dtype=torch.uint8, device="cuda")
+    nn.conv3x3_wgrad(x, dy, dw, db, scratch)
+    torch.cuda.synchronize()
+    _, ref_w, ref_b = U.conv3x3_backward(x64, np.zeros((cout, 9, cin)), dy64)
+    _, S_w, S_b = U.conv3x3_backward(np.abs(x64), np.zeros((cout, 9, cin)), np.abs(dy64))
+    assert_close(dw.cpu().numpy().astype(np.float64), ref_w, S_w, rel=0.0, what="dw")
+    assert_close(db.cpu().numpy().astype(np.float64), ref_b, S_b, rel=0.0, what="db")
+
+
+def test_pool_upsample_and_adjoints():
+    announce("nn pool / upsample")
+    rng = np.random.default_rng(40)
+    B, H, W, C = 2, 12, 18, 16
+    x, x64 = bf(rng.standard_normal((B, H, W, C)))
+    y = torch.empty((B, H // 2, W // 2, C), dtype=torch.bfloat16, device="cuda")
+    nn.avgpool2(x, y)
+    up = torch.empty((B, H, W, C), dtype=torch.bfloat16, device="cuda")
+    nn.upsample2(y, up)
+    torch.cuda.synchronize()
+    ref = U.avgpool2(x64)
+    assert_close(back(y), ref, U.avgpool2(np.abs(x64)), what="avgpool")
+    assert np.array_equal(back(up), U.upsample2(back(y)))
+    # adjoints: pooling backward (masked, accumulated) and upsampling backward (masked)
+    dy, dy64 = bf(rng.standard_normal((B, H // 2, W // 2, C)))
+    old, old64 = bf(rng.standard_normal((B, H, W, C)))
+    mfine, mfine64 = bf(np.maximum(rng.standard_normal((B, H, W, C)), 0.0))
+    nn.avgpool2_backward(dy, old, mask=mfine, accumulate=True)
+    dfine, dfine64 = bf(rng.standard_normal((B, H, W, C)))
+    mco, mco64 = bf(np.maximum(rng.standard_normal((B, H // 2, W // 2, C)), 0.0))
+    dco = torch.empty((B, H // 2, W // 2, C), dtype=torch.bfloat16, device="cuda")
+    nn.upsample2_backward(dfine, dco, mask=mco)
+    torch.cuda.synchronize()
+    ref = (old64 + U.avgpool2_backward(dy64)) * (mfine64 > 0)
+    assert_close(back(old), ref, np.abs(old64) + 0.25 * U.upsample2(np.abs(dy64)), what="pool backward")
+    ref = U.upsample2_backward(dfine64) * (mco64 > 0)
+    assert_close(back(dco), ref, U.upsample2_backward(np.abs(dfine64)), what="upsample backward")
+
+
+def test_head_loss_and_adam():
+    announce("nn head / loss / adam")
+    rng = np.random.default_rng(50)
+    B, H, W, C = 2, 20, 24, 32
+    x, x64 = bf(np.maximum(rng.standard_normal((B, H, W, C)), 0.0))
+    w, w64 = bf(rng.standard_normal(C))
+    b, b64 = f32([0.3])
+    r = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    nn.head(x, w, b, r)
+    t, t64 = f32(rng.standard_normal((B, H, W)))
+    mask_np = (rng.random((H, W)) > 0.25).astype(np.uint8)
+    mask = torch.from_numpy(mask_np).cuda()
+    dr = torch.empty_like(r)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    nn.masked_mse(r, t, mask, dr, out, torch.empty(nn.mse_scratch_bytes(), dtype=torch.uint8, device="cuda"))
+    dx = torch.empty((B, H, W, C), dtype=torch.bfloat16, device="cuda")
+    dw = torch.empty(C, dtype=torch.float32, device="cuda")
+    db = torch.empty(1, dtype=torch.float32, device="cuda")
+    nn.head_backward(x, w, dr, dx, dw, db, torch.empty(nn.head_scratch_bytes(C), dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    r64 = U.head(x64, w64, b64[0])
+    assert_close(r.cpu().numpy().astype(np.float64), r64, U.head(np.abs(x64), np.abs(w64), 0.3), rel=0.0, what="head")
+    L, dr_ref = U.masked_mse(r.cpu().numpy().astype(np.float64), t64, mask_np.astype(bool))
+    assert abs(float(out[0].item()) - L) <= 1e-12 * L and float(out[1].item()) == B * mask_np.sum()
+    assert np.allclose(dr.cpu().numpy(), dr_ref, rtol=1e-6, atol=1e-12)
+    dr64 = dr.cpu().numpy().astype(np.float64)
+    dx_ref, dw_ref, db_ref = U.head_backward(x64, w64, dr64)
+    dx_ref = U.relu_backward(x64, dx_ref)
+    assert_close(back(dx), dx_ref, np.abs(dx_ref), acc=0.0, what="head dx")
+    _, S_w, S_b = U.head_backward(np.abs(x64), w64, np.abs(dr64))
+    assert_close(dw.cpu().numpy().astype(np.float64), dw_ref, S_w, rel=0.0, what="head dw")
+    assert abs(float(db.item()) - db_ref) <= ACC * S_b
+    # Adam: three steps against the oracle's update
+    n = 1000
+    w0, w064 = f32(rng.standard_normal(n))
+    m = torch.zeros(n, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    wb = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    wr, mr, vr = w064.copy(), np.zeros(n), np.zeros(n)
+    for step in (1, 2, 3):
+        g, g64 = f32(rng.standard_normal(n))
+        nn.adam(w0, g, m, v, wb, step, 1e-2)
+        wr, mr, vr = U.adam_step(wr, g64, mr, vr, step, 1e-2)
+    torch.cuda.synchronize()
+    assert np.allclose(w0.cpu().numpy(), wr, rtol=0, atol=1e-5)
+    assert np.array_equal(back(wb), U.bf16_round(w0.cpu().numpy()))
+
+
+def test_pack_input_symmetries():
+    announce("nn pack input")
+    rng = np.random.default_rng(60)
+    H = W = 16
+    K = 3
+    c, c64 = f32(1500 + 60 * rng.standard_normal((H, W)))
+    g, g64 = f32(rng.standard_normal((K, H, W)))
+    ct, ct64 = f32(1500 + 60 * rng.standard_normal((H, W)))
+    x = torch.empty((1, H, W, 8), dtype=torch.bfloat16, device="cuda")
+    base = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    tgt = torch.empty_like(base)
+    scratch = torch.empty(nn.pack_scratch_bytes(), dtype=torch.uint8, device="cuda")
+    gs = g64.sum(0)
+    for sym in range(8):
+        nn.pack_input(c, g, ct, sym, 1500.0, 100.0, x, base, tgt, scratch)
+        torch.cuda.synchronize()
+        # output (i, j) reads T's source pixel: flips act on the output index before the transpose
+        def src(a):
+            out = np.empty_like(a)
+            for i in range(H):
+                for j in range(W):
+                    ii, jj = (H - 1 - i if sym & 1 else i), (W - 1 - j if sym & 2 else j)
+                    if sym & 4:
+                        ii, jj = jj, ii
+                    out[i, j] = a[ii, jj]
+            return out
+        xs = back(x)[0]
+        assert_close(xs[..., 0], src((c64 - 1500.0) / 100.0), np.abs(src((c64 - 1500.0) / 100.0)), acc=0.0)
+        assert_close(xs[..., 1], src(gs / np.abs(gs).max()), np.ones((H, W)), acc=1e-6)
+        assert np.all(xs[..., 2:] == 0.0)
+        assert np.array_equal(base.cpu().numpy(), src(c64).astype(np.float32))
+        assert np.allclose(tgt.cpu().numpy(), src((ct64 - c64) / 100.0), rtol=1e-6, atol=1e-6)
+
+
+def _oracle_params(net, seed, base):
+    """Oracle parameters equal to the GPU network's (bf16 weights, float32 biases)."""
+    rng = np.random.default_rng(seed)
+    p = U.init_params(net.cin, base, seed)
+    for k in list(p):
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    p["head.w"] = rng.standard_normal(base) / np.sqrt(base)
+    p["head.b"] = np.array([0.1])
+    net.load(p)
+    st = net.state()
+    out = {}
+    for k, v in st.items():
+        v = v.astype(np.float64)
+        out[k] = U.bf16_round(v) if k.endswith(".w") else v
+    return out
+
+
+@pytest.mark.parametrize("shape", [(2, 32, 32, 8), (1, 64, 64, 32)])
+def test_network_forward_and_gradient_match_oracle(shape):
+    B, H, W, base = shape
+    announce(f"nn whole network B={B} {H}x{W} base={base}")
+    net = learned.UNet(base=base, seed=1)
+    p = _oracle_params(net, 70 + base, base)
+    rng = np.random.default_rng(80 + base)
+    x, x64 = bf(np.concatenate([rng.standard_normal((B, H, W, 2)), np.zeros((B, H, W, 6))], axis=-1))
+    t, t64 = f32(rng.standard_normal((B, H, W)))
+    mask_np = np.ones((H, W), dtype=np.uint8)
+    mask_np[: H // 8] = 0
+    mask = torch.from_numpy(mask_np).cuda()
+    r = net.forward(x)
+    dr = torch.empty_like(r)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    nn.masked_mse(r, t, mask, dr, out, torch.empty(nn.mse_scratch_bytes(), dtype=torch.uint8, device="cuda"))
+    net.backward(dr)
+    torch.cuda.synchronize()
+    # the oracle in the layers' storage precision (every kept tensor rounded to
+    # bf16, so ReLU decisions see the same values) and in full precision
+    r_ref, cache = U.unet_forward(p, x64, store=U.bf16_round)
+    r_got = r.cpu().numpy().astype(np.float64)
+    dr_got = dr.cpu().numpy().astype(np.float64)
+    g_ref = U.unet_backward(p, cache, dr_got, store=U.bf16_round)
+    r_full, cache_full = U.unet_forward(p, x64)
+    L_full, dr_full = U.masked_mse(r_full, t64, mask_np.astype(bool))
+    g_full = U.unet_backward(p, cache_full, dr_full)
+    L_ref, _ = U.masked_mse(r_ref, t64, mask_np.astype(bool))
+    e_r = np.linalg.norm(r_got - r_ref) / np.linalg.norm(r_ref)
+    e_L = abs(float(out[0].item()) - L_ref) / L_ref
+    g_got = net.grad.cpu().numpy().astype(np.float64)
+
+    def flat(g):
+        parts = []
+        for name in [n for n, _, _ in net.table]:
+            parts += [g[name + ".w"].reshape(-1), g[name + ".b"].reshape(-1)]
+        return np.concatenate(parts + [g["head.w"].reshape(-1), np.asarray(g["head.b"]).reshape(-1)])
+
+    got = np.concatenate([g_got[:net.head_off], g_got[net.head_off:]])
+    errs = {}
+    for name in [n for n, _, _ in net.table]:
+        o, ob, co = net.offsets[name]
+        gr = g_ref[name + ".w"].reshape(-1)
+        errs[name] = float(np.linalg.norm(g_got[o:ob] - gr) / max(np.linalg.norm(gr), 1e-30))
+    e_all = float(np.linalg.norm(got - flat(g_ref)) / np.linalg.norm(flat(g_ref)))
+    gap_r = float(np.linalg.norm(r_ref - r_full) / np.linalg.norm(r_full))
+    gap_g = float(np.linalg.norm(flat(g_ref) - flat(g_full)) / np.linalg.norm(flat(g_full)))
+    worst = max(errs, key=errs.get)
+    print(f"[nn] {shape}: vs bf16-storage oracle: output rel {e_r:.2e}, loss rel {e_L:.2e}, gradient rel "
+          f"{e_all:.2e}, worst layer {worst} {errs[worst]:.2e}; bf16 storage vs full precision: output "
+          f"{gap_r:.2e}, gradient {gap_g:.2e}, loss {abs(L_ref - L_full) / L_full:.2e}", flush=True)
+    assert e_r <= 2e-2 and e_L <= 1e-2
+    assert e_all <= 0.1
+    assert max(errs.values()) <= 0.2
+    assert gap_r <= 2e-2 and gap_g <= 0.15
+
+
+def test_network_forward_full_size_matches_oracle():
+    """The fine-level size of the learned start: one 512 x 512 image, base 32."""
+    announce("nn whole network forward 1x512x512 base 32")
+    net = learned.UNet(base=32, seed=2)
+    p = _oracle_params(net, 90, 32)
+    rng = np.random.default_rng(91)
+    x, x64 = bf(np.concatenate([rng.standard_normal((1, 512, 512, 2)), np.zeros((1, 512, 512, 6))], axis=-1))
+    r = net.forward(x)
+    torch.cuda.synchronize()
+    r_ref, _ = U.unet_forward(p, x64, store=U.bf16_round)
+    e = float(np.linalg.norm(r.cpu().numpy() - r_ref) / np.linalg.norm(r_ref))
+    print(f"[nn] 512x512 forward rel {e:.2e} (bf16-storage oracle)", flush=True)
+    assert e <= 2e-2

@@ -1,24 +1,28 @@
 """The C-ABI library loads and exports every entry point declared in
-include/pat.h (no GPU needed: nothing is computed)."""
+include/pat.h and include/pat_nn.h (no GPU needed: nothing is computed)."""
 import ctypes
 import os
 import re
 
 import pytest
 
-from paper_2505_08482_amd import pat
+from paper_2505_08482_amd import nn, pat
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "pat.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pat_[a-z_0-9]+)\s*\(", src)))
+def _declared(header=None):
+    names = set()
+    for h in ([header] if header else ["pat.h", "pat_nn.h"]):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(pat_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_and_binding_agree():
-    assert _declared() == sorted(pat.EXPORTS)
+    assert _declared("pat.h") == sorted(pat.EXPORTS)
+    assert _declared("pat_nn.h") == sorted(nn.EXPORTS)
 
 
 @pytest.mark.skipif(not os.path.exists(pat.LIB_PATH), reason="libpat.so not built")
@@ -64,3 +68,33 @@ def test_host_side_argument_checks():
     empty = (ctypes.c_uint8 * 64)()
     assert L.pat_ou_create(8, 8, 1e-4, 1e-3, empty, ctypes.byref(oh)) == pat.PAT_EINVAL   # empty mask
     assert L.pat_ou_create(300, 300, 1e-4, 1e-3, None, ctypes.byref(oh)) == pat.PAT_EUNSUPPORTED   # L > 512
+
+
+@pytest.mark.skipif(not os.path.exists(pat.LIB_PATH), reason="libpat.so not built")
+def test_nn_host_side_argument_checks():
+    """The learned-start layers refuse bad shapes, misaligned pointers and short
+    scratch before launching anything."""
+    L = nn.lib()
+    d16 = ctypes.c_void_p(1 << 20)        # 16-byte aligned stand-in, never dereferenced
+    odd = ctypes.c_void_p((1 << 20) + 2)  # misaligned
+    # cin not a multiple of 8, ld below the channel count, misaligned input
+    assert L.pat_nn_conv3x3(1, 8, 8, d16, 12, 12, d16, None, d16, 32, 32, 1, 0, None, 0, None) == pat.PAT_EINVAL
+    assert L.pat_nn_conv3x3(1, 8, 8, d16, 8, 16, d16, None, d16, 32, 32, 1, 0, None, 0, None) == pat.PAT_EINVAL
+    assert L.pat_nn_conv3x3(1, 8, 8, odd, 16, 16, d16, None, d16, 32, 32, 1, 0, None, 0, None) == pat.PAT_EINVAL
+    assert L.pat_nn_conv3x3(0, 8, 8, d16, 16, 16, d16, None, d16, 32, 32, 1, 0, None, 0, None) == pat.PAT_EINVAL
+    size = ctypes.c_size_t(0)
+    assert L.pat_nn_wgrad_scratch_bytes(2, 16, 16, 32, 64, ctypes.byref(size)) == pat.PAT_OK and size.value > 0
+    need = size.value
+    assert L.pat_nn_conv3x3_wgrad(2, 16, 16, d16, 32, 32, d16, 64, 64, d16, None, d16, need - 4,
+                                  None) == pat.PAT_EWORKSPACE
+    assert L.pat_nn_conv3x3_wgrad(2, 16, 16, d16, 32, 32, d16, 64, 60, d16, None, d16, need, None) == pat.PAT_EINVAL
+    assert L.pat_nn_avgpool2(1, 7, 8, 8, d16, 8, d16, 8, None) == pat.PAT_EINVAL          # odd height
+    assert L.pat_nn_upsample2(1, 8, 8, 12, d16, 16, d16, 16, None) == pat.PAT_EINVAL      # C % 8
+    assert L.pat_nn_head_backward(10, 24, d16, 24, d16, d16, d16, 24, d16, d16, d16, 1 << 20,
+                                  None) == pat.PAT_EINVAL                                # 24 does not divide 256
+    assert L.pat_nn_masked_mse(1, 16, d16, d16, d16, d16, d16, d16, 8, None) == pat.PAT_EWORKSPACE
+    assert L.pat_nn_adam(10, d16, d16, d16, d16, None, 0, 1e-3, 0.9, 0.999, 1e-8, None) == pat.PAT_EINVAL
+    assert L.pat_nn_pack_input(8, 16, 1, d16, d16, None, 4, 1500.0, 100.0, d16, d16, None, d16, 1 << 12,
+                               None) == pat.PAT_EINVAL                                   # transpose of a non-square
+    assert L.pat_nn_pack_input(8, 8, 1, d16, d16, None, 0, 1500.0, 100.0, d16, d16, d16, d16, 1 << 12,
+                               None) == pat.PAT_EINVAL                                   # target without c_true
