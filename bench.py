@@ -343,6 +343,37 @@ def time_to_solution(wl_fine, c_true, y_fine, w, iters: int, target: float = 2.0
                         "E_c_last": round(lv.E_c[-1], 3) if lv.E_c else None} for lv in out["levels"]]}
 
 
+def learned_start(cases, fine_iters: int = 20, targets=(2.0, 1.0)):
+    """Held-out phantoms (the 256^2 workload's generators at 512^2, K = 8,
+    seeds 5000 + case): plain multigrid 128 -> 256 -> 512 against the coarse
+    level followed by the fine level started from the trained network's
+    proposal (and, for the gain of the network alone, from the plain
+    interpolation of the same coarse iterate).  Iterations and wall time from
+    the start of each run to E_c <= each target on the finest grid."""
+    import os as _os
+    from paper_2505_08482_amd import learned
+    if not _os.path.exists(learned.DEFAULT_WEIGHTS):
+        return {"error": "no trained weights in the package"}
+    net = learned.load_weights(learned.DEFAULT_WEIGHTS)
+    rows = [learned.evaluate_case(net, c, fine_iters=fine_iters, targets=targets) for c in cases]
+    summary = {}
+    for run in ("plain_multigrid", "interpolated", "learned"):
+        for tg in targets:
+            hits = [r[run]["to_target"][f"{tg:g}"] for r in rows]
+            ok = [h for h in hits if h is not None]
+            summary[f"{run}@{tg:g}%"] = {
+                "reached": f"{len(ok)}/{len(rows)}",
+                "mean_seconds": round(float(np.mean([h["seconds"] for h in ok])), 2) if ok else None,
+                "mean_iterations": round(float(np.mean([h["iterations"] for h in ok])), 1) if ok else None}
+    for r in rows:            # keep the JSON line short: trajectories stay in the rows' summaries
+        for run in ("plain_multigrid", "interpolated", "learned"):
+            r[run].pop("t", None)
+    return {"targets_E_c_percent": list(targets), "cases": list(cases), "summary": summary,
+            "mean_E_c_fine_start": {k: round(float(np.mean([r[k]["E_c_start"] for r in rows])), 3)
+                                    for k in ("interpolated", "learned")},
+            "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +391,8 @@ def main() -> int:
                     help="skip the checkpointed, batch and time-to-solution measurements")
     ap.add_argument("--batch-evals", type=int, default=5)
     ap.add_argument("--tts-iters", type=int, default=40)
+    ap.add_argument("--learned-cases", type=int, default=2,
+                    help="held-out phantoms for the learned-start comparison (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -480,7 +513,9 @@ def main() -> int:
                          ("checkpointed", lambda: checkpointed(plan, wl, c, t_p0, y, w, evaluation_ms=ms)),
                          ("batch", lambda: batch_w3(args.batch_evals)),
                          ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters)),
-                         ("paper_geometry", lambda: paper_geometry(args.tts_iters))):
+                         ("paper_geometry", lambda: paper_geometry(args.tts_iters)),
+                         ("learned_start", lambda: learned_start(range(args.learned_cases))
+                          if args.learned_cases > 0 else {"skipped": True})):
             try:
                 out[name] = fn()
             except Exception as e:   # an extra must never cost the main line

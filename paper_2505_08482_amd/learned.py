@@ -17,6 +17,7 @@ bfloat16 for the kernels with float32 master copies for Adam.
 from __future__ import annotations
 
 import dataclasses
+import os
 import time
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -241,6 +242,7 @@ class UNet:
 # Training pairs generated by the method itself
 # ---------------------------------------------------------------------------
 COARSE_N, FINE_N = 128, 512
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_c512_k8.npz")
 
 
 def pair_phantoms(wl: I.Workload, j: int):
@@ -342,8 +344,8 @@ class LearnedStart:
 def train(net: UNet, coarse_c: torch.Tensor, coarse_g: torch.Tensor, c_true: torch.Tensor, fine: I.Workload,
           coarse_dx: float, epochs: int, batch: int = 4, lr: float = 1e-3, seed: int = 0, log=None,
           symmetries: Sequence[int] = tuple(range(8)), time_budget: Optional[float] = None) -> List[float]:
-    """Adam on the masked squared error of the correction (in units of
-    C_SCALE) over pairs (coarse c [n][h][w], summed p0 gradient [n][h][w],
+    """Adam (step size decayed on a cosine from ``lr`` to 0) on the masked
+    squared error of the correction (in units of C_SCALE) over pairs (coarse c [n][h][w], summed p0 gradient [n][h][w],
     true fine c [n][H][W]); every pair is used under each symmetry of the
     square in ``symmetries`` (the sensor ring and grids share them)."""
     g = fine.grid
@@ -375,7 +377,12 @@ def train(net: UNet, coarse_c: torch.Tensor, coarse_g: torch.Tensor, c_true: tor
             r = net.forward(X)
             nn.masked_mse(r, target, mask, dr, out, mse_scratch)
             net.backward(dr)
-            net.adam(lr)
+            # cosine decay of the step size over the run (by time if budgeted, else by epochs)
+            if time_budget is not None:
+                frac = min(1.0, (time.perf_counter() - t0) / time_budget)
+            else:
+                frac = (ep + start / len(order)) / epochs
+            net.adam(lr * 0.5 * (1.0 + np.cos(np.pi * frac)))
             tot += float(out[0].item())
             cnt += 1
             if time_budget is not None and time.perf_counter() - t0 > time_budget:
@@ -388,15 +395,30 @@ def train(net: UNet, coarse_c: torch.Tensor, coarse_g: torch.Tensor, c_true: tor
     return losses
 
 
-def save_weights(net: UNet, path: str) -> None:
+def save_weights(net: UNet, path: str, bf16: bool = True) -> None:
+    """``.npz`` of the parameters by name; with ``bf16`` the convolution and
+    head weights are stored as their bfloat16 bit patterns (uint16): exactly
+    what the kernels use, at half the size (biases stay float32)."""
     st = net.state()
+    if bf16:
+        for k in st:
+            if k.endswith(".w"):
+                u = st[k].astype(np.float32).view(np.uint32).astype(np.uint64)
+                st[k] = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
     np.savez_compressed(path, base=np.array([net.base]), cin=np.array([net.cin]), **st)
 
 
 def load_weights(path: str, device: str = "cuda") -> UNet:
+    """Network from ``save_weights`` (bfloat16 bit patterns widen exactly to float32)."""
     with np.load(path, allow_pickle=False) as f:
         net = UNet(base=int(f["base"][0]), cin=int(f["cin"][0]), device=device)
-        net.load({k: f[k] for k in f.files if k not in ("base", "cin")})
+        st = {}
+        for k in f.files:
+            if k in ("base", "cin"):
+                continue
+            v = f[k]
+            st[k] = (v.astype(np.uint32) << 16).view(np.float32) if v.dtype == np.uint16 else v
+        net.load(st)
     return net
 
 
@@ -444,64 +466,74 @@ def first_at(E: Sequence[float], T: Sequence[float], target: float):
     return None, None
 
 
+def _hits(E: Sequence[float], T: Sequence[float], targets: Sequence[float], its_before: int, offset: int):
+    """Per target: total iterations and seconds at the first E_c <= target."""
+    out = {}
+    for tg in targets:
+        i, t = first_at(E, T, tg)
+        out[f"{tg:g}"] = None if i is None else {"iterations": its_before + i + offset, "seconds": round(t, 2)}
+    return out
+
+
 def evaluate_case(net: Optional[UNet], case: int, K: int = 8, coarse_iters: int = 40, fine_iters: int = 20,
-                  target: float = 2.0, plain_multigrid: bool = True, log=None) -> Dict:
+                  targets: Sequence[float] = (2.0, 1.0), plain_multigrid: bool = True, log=None) -> Dict:
     """One held-out phantom (the 256^2 workload's generators at 512^2, seeds
     5000 + case): plain multigrid 128 -> 256 -> 512 against the coarse level
     followed directly by the fine level, started from the plain interpolation
-    of the coarse iterate and from the network's proposal."""
+    of the coarse iterate and from the network's proposal.  For each start:
+    E_c at the fine start and after every fine iteration, and the iterations
+    and wall time (from the start of the run) at which E_c first falls to each
+    target; the fine level stops at the smallest target."""
     from . import recon
     fine = I.config3_level(FINE_N, K=K)
     c_np, p0_np = I.phantoms(fine, 5, case=case)
     c_true = torch.from_numpy(c_np.astype(np.float32)).cuda()
     y, w = simulate(fine, c_np, p0_np, noise_seed=5000 + case + 500)
     dt = fine.grid.dt
-    mask = torch.from_numpy(fine.mask().astype(np.bool_)).cuda()
     res: Dict = {"case": case}
+    stop = min(targets) if targets else None
     # coarse level, shared by both starts
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     co = coarse_level(y, dt, w, K, iters=coarse_iters)
     c_up, g_up = fine_inputs(co, fine)
-    src = co.p0.contiguous()
     p0_up = torch.empty((K, fine.grid.ny, fine.grid.nx), dtype=torch.float32, device="cuda")
-    pat.prolong_phys(src, co.dx, p0_up, fine.grid.dx)
+    pat.prolong_phys(co.p0.contiguous(), co.dx, p0_up, fine.grid.dx)
+    torch.cuda.synchronize()
     t_coarse = time.perf_counter() - t0
     res["coarse_seconds"] = round(t_coarse, 3)
-    starts = {"interpolated": c_up.clone()}
+    res["coarse_iterations"] = co.iters
+    starts = {"interpolated": (c_up.clone(), 0.0)}
     if net is not None:
-        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        starts["learned"] = LearnedStart(net, fine)(c_up, g_up).clone()
+        c_net = LearnedStart(net, fine)(c_up, g_up).clone()
         torch.cuda.synchronize()
         res["network_seconds"] = round(time.perf_counter() - t1, 4)
-    for name, c0 in starts.items():
-        t_start = time.perf_counter() - (t_coarse + (res.get("network_seconds", 0.0) if name == "learned" else 0.0))
-        E, T = fine_level(fine, y, w, c0, p0_up, c_true, fine_iters, target=target, t_origin=t_start)
-        i, t = first_at(E, T, target)
+        starts["learned"] = (c_net, time.perf_counter() - t1)
+    for name, (c0, extra) in starts.items():
+        t_origin = time.perf_counter() - (t_coarse + extra)
+        E, T = fine_level(fine, y, w, c0, p0_up, c_true, fine_iters, target=stop, t_origin=t_origin)
         res[name] = {"E_c_start": round(E[0], 3), "E_c_last": round(E[-1], 3), "fine_iterations": len(E) - 1,
-                     "fine_iterations_to_target": i, "seconds_to_target": None if t is None else round(t, 2),
-                     "iterations_to_target": None if i is None else co.iters + i}
+                     "E_c": [round(e, 3) for e in E], "t": [round(t, 2) for t in T],
+                     "to_target": _hits(E, T, targets, co.iters, 0)}
         if log:
-            log(f"case {case} {name}: E_c start {E[0]:.3f} % -> {E[-1]:.3f} %, target at fine iteration {i} "
-                f"({'-' if t is None else f'{t:.2f} s'})")
+            log(f"case {case} {name}: E_c start {E[0]:.3f} % -> {E[-1]:.3f} % after {len(E) - 1} fine "
+                f"iterations; {res[name]['to_target']}")
     if plain_multigrid:
         levels = [I.config3_level(n, K=K) for n in (COARSE_N, 256, FINE_N)]
-        hit = {}
-
-        def cb(msg):
-            pass
+        torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out = recon.multigrid(levels, y, dt, w, c_true, iters=coarse_iters, log=cb)
+        out = recon.multigrid(levels, y, dt, w, c_true, iters=coarse_iters)
         total = time.perf_counter() - t2
         fl = out["levels"][-1]
         its_before = sum(lv.iters for lv in out["levels"][:-1])
-        i, t = first_at(fl.E_c, fl.t, target)
-        if i is not None:
-            hit = {"iterations_to_target": its_before + i + 1, "seconds_to_target": round(fl.t_start + t, 2)}
-        res["plain_multigrid"] = {"E_c_fine_start": None, "E_c_last": round(out["E_c"], 3),
-                                  "seconds_total": round(total, 2), **hit}
+        T = [fl.t_start + t for t in fl.t]
+        res["plain_multigrid"] = {"E_c_last": round(out["E_c"], 3), "seconds_total": round(total, 2),
+                                  "E_c": [round(e, 3) for e in fl.E_c], "t": [round(t, 2) for t in T],
+                                  "to_target": _hits(fl.E_c, T, targets, its_before, 1)}
         if log:
-            log(f"case {case} plain multigrid: final E_c {out['E_c']:.3f} %, {hit or 'target not reached'}")
+            log(f"case {case} plain multigrid: final E_c {out['E_c']:.3f} % in {total:.1f} s; "
+                f"{res['plain_multigrid']['to_target']}")
     return res
 
 
@@ -529,8 +561,12 @@ def generate_pairs(start: int, count: int, K: int = 8, coarse_iters: int = 40, l
 
 
 def truth_for_pairs(index: Sequence[int], K: int = 8) -> np.ndarray:
+    """True 512^2 sound speeds of training pairs (the sound-speed draw of
+    ``pair_phantoms`` alone)."""
     fine = I.config3_level(FINE_N, K=K)
-    return np.stack([pair_phantoms(fine, int(j))[0] for j in index]).astype(np.float32)
+    n = fine.grid.nx
+    return np.stack([I.grf_c(n, np.random.default_rng([5, 1, int(j)]), fine.support_radius_px,
+                             corr_px=20.0 * n / 256.0) for j in index]).astype(np.float32)
 
 
 def main(argv=None) -> int:

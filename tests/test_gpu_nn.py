@@ -68,6 +68,8 @@ CONV_CASES = [
     (1, 9, 30, 96, 96, (0, 96), (0, 96)),       # two output tiles, the second half full
     (1, 16, 16, 64, 32, (16, 96), (32, 96)),    # channel slices of wider buffers
     (3, 8, 8, 128, 256, (0, 128), (0, 256)),
+    (1, 16, 16, 384, 128, (0, 384), (0, 128)),  # the network's widest layer (decoder, 128^2 level)
+    (1, 8, 8, 256, 256, (0, 256), (0, 256)),    # the bottom layer
 ]
 
 
@@ -125,6 +127,8 @@ WGRAD_CASES = [
     (1, 33, 31, 8, 32, (0, 8), (0, 32)),        # 72 (tap, ci) columns: two column tiles
     (2, 16, 16, 96, 32, (0, 96), (0, 32)),
     (1, 24, 24, 64, 128, (64, 192), (0, 128)),  # input is a slice of a concatenation
+    (1, 16, 16, 384, 128, (0, 384), (0, 128)),  # the network's widest layer
+    (2, 8, 8, 256, 256, (0, 256), (64, 384)),   # the bottom layer, gradient a slice
 ]
 
 
