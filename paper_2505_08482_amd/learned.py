@@ -569,6 +569,55 @@ def truth_for_pairs(index: Sequence[int], K: int = 8) -> np.ndarray:
                              corr_px=20.0 * n / 256.0) for j in index]).astype(np.float32)
 
 
+def network_flops(net: UNet, B: int, H: int, W: int) -> Tuple[float, float]:
+    """Multiply-add flops (2 per product) of the 3x3 convolutions: forward, and
+    forward + both backward contractions (data gradient skipped for the first
+    layer, whose input needs none)."""
+    fwd = bwd = 0.0
+    for name, ci, co in net.table:
+        lvl = int(name[1])
+        f = 2.0 * B * (H >> lvl) * (W >> lvl) * 9 * ci * co
+        fwd += f
+        bwd += f if name == "e0a" else 2.0 * f
+    return fwd, fwd + bwd
+
+
+def time_network(B: int = 4, steps: int = 5, H: int = FINE_N, W: int = FINE_N) -> Dict:
+    """Average wall time of the forward pass and of one training step (forward,
+    loss, backward, Adam) on random inputs, and the convolution flop rates."""
+    net = load_weights(DEFAULT_WEIGHTS) if os.path.exists(DEFAULT_WEIGHTS) else UNet(base=32)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((B, H, W, CIN), device="cuda", generator=g).to(torch.bfloat16)
+    t = torch.randn((B, H, W), device="cuda", generator=g)
+    mask = torch.ones((H, W), dtype=torch.uint8, device="cuda")
+    dr = torch.empty_like(t)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    sc = torch.empty(nn.mse_scratch_bytes(), dtype=torch.uint8, device="cuda")
+
+    def step():
+        r = net.forward(x)
+        nn.masked_mse(r, t, mask, dr, out, sc)
+        net.backward(dr)
+        net.adam(1e-5)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / steps
+    ff, ft = network_flops(net, B, H, W)
+    return {"batch": B, "size": [H, W], "forward_ms": round(1e3 * tf, 3), "train_step_ms": round(1e3 * ts, 3),
+            "forward_conv_TFLOPs": round(ff / tf / 1e12, 1), "train_conv_TFLOPs": round(ft / ts / 1e12, 1),
+            "forward_GFLOP": round(ff / 1e9, 2), "train_GFLOP": round(ft / 1e9, 2)}
+
+
 def main(argv=None) -> int:
     import argparse
     import json
@@ -586,6 +635,9 @@ def main(argv=None) -> int:
     t.add_argument("--minutes", type=float, default=None, help="stop after this much training time")
     t.add_argument("--holdout", type=int, default=0, help="pairs kept out of training for a validation loss")
     t.add_argument("--out", required=True)
+    tm = sub.add_parser("time", help="time the network's forward pass and training step at 512^2")
+    tm.add_argument("--batch", type=int, default=4)
+    tm.add_argument("--steps", type=int, default=5)
     e = sub.add_parser("eval", help="held-out phantoms: learned start vs plain multigrid")
     e.add_argument("--weights", default=None)
     e.add_argument("--cases", type=int, nargs="+", default=[0, 1])
@@ -627,6 +679,9 @@ def main(argv=None) -> int:
                 e0.append(relative_error(c_up[0], ct, mask))
                 e1.append(relative_error(ls(c_up[0], c_up[1:2]), ct, mask))
             log(f"held-out pairs: E_c interpolated {np.mean(e0):.3f} %, learned {np.mean(e1):.3f} %")
+        return 0
+    if a.cmd == "time":
+        print(json.dumps(time_network(a.batch, a.steps)), flush=True)
         return 0
     if a.cmd == "eval":
         net = load_weights(a.weights) if a.weights else None

@@ -55,6 +55,7 @@ def test_batch_equals_single_runs_bitwise(K):
     c, p0, r = _inputs(wl, seed=3)
     announce(f"batch K={K} vs singles")
     full = gpu_forward_adjoint(wl, c, p0, resid32=r)
+    w1 = dataclasses.replace(wl, K=1, name=wl.name + "_single")
     gc_sum = np.zeros(full["g_c"].shape, dtype=np.float64)
     for k in range(wl.K):
         one = gpu_forward_adjoint(w1, c, p0[k:k + 1], resid32=np.ascontiguousarray(r[k:k + 1]))
