@@ -40,6 +40,11 @@ HBM_PEAK_GBS = 8000.0
 ADJ_KB = 4      # datasets per block of that pass at K >= 4
 
 
+def progress(msg: str) -> None:
+    """One line per finished step on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
 def pass_bytes(K: int) -> dict:
     kb = ADJ_KB if K >= 4 else (2 if K >= 2 else 1)
     c_amort = 4.0 / K
@@ -355,7 +360,8 @@ def learned_start(cases, fine_iters: int = 20, targets=(2.0, 1.0)):
     if not _os.path.exists(learned.DEFAULT_WEIGHTS):
         return {"error": "no trained weights in the package"}
     net = learned.load_weights(learned.DEFAULT_WEIGHTS)
-    rows = [learned.evaluate_case(net, c, fine_iters=fine_iters, targets=targets) for c in cases]
+    rows = [learned.evaluate_case(net, c, fine_iters=fine_iters, targets=targets,
+                                  log=lambda m: progress("learned_start " + m)) for c in cases]
     summary = {}
     for run in ("plain_multigrid", "interpolated", "learned"):
         for tg in targets:
@@ -450,6 +456,7 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = 1000.0 * wall / args.steps          # wall clock between the two synchronizations
+    progress(f"timed {args.steps} evaluations: {ms:.1f} ms each")
     # Per-pass durations: start/stop HIP events attached to sampled dispatches of
     # every pass kind, on the stream they run on.  Events cannot sit inside the captured
     # step graphs, so this evaluation (right after the timed ones, same inputs
@@ -516,14 +523,19 @@ def main() -> int:
                          ("paper_geometry", lambda: paper_geometry(args.tts_iters)),
                          ("learned_start", lambda: learned_start(range(args.learned_cases))
                           if args.learned_cases > 0 else {"skipped": True})):
+            progress(f"{name} ...")
             try:
                 out[name] = fn()
             except Exception as e:   # an extra must never cost the main line
                 out[name] = {"error": f"{type(e).__name__}: {e}"}
+            progress(f"{name} done")
     if not args.no_cpu:
+        progress("cpu_baseline ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, wl.K)
+        progress("cpu_baseline done")
         if not args.no_extras:
             out["cpu_baseline_single_core"] = cpu_baseline(max(2, args.cpu_steps // 4), wl.K, cores=1)
+            progress("cpu_baseline_single_core done")
     print(json.dumps(out), flush=True)
     plan.close()
     return 0
