@@ -28,14 +28,17 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // pixel-split of the weight gradient: enough blocks to fill the chip, whole chunks per split
 struct WgradSplit {
-  int ntiles, cotiles;
+  int ct, ntiles, cotiles;
   int64_t nchunks, per, nsplit;
 };
 
+// output-channel tile 32 for layers of at most 32 channels (128 columns per block), else 64 (64 columns)
 WgradSplit wgrad_split(int64_t P, int cin, int cout) {
   WgradSplit s;
-  s.ntiles = (9 * cin + 63) / 64;
-  s.cotiles = (cout + 63) / 64;
+  s.ct = cout <= 32 ? 32 : 64;
+  const int nt = s.ct == 32 ? WgradTile<32>::NT : WgradTile<64>::NT;
+  s.ntiles = (9 * cin + nt - 1) / nt;
+  s.cotiles = (cout + s.ct - 1) / s.ct;
   s.nchunks = (P + WG_CHUNK - 1) / WG_CHUNK;
   const int64_t tiles = (int64_t)s.ntiles * s.cotiles;
   int64_t want = (2048 + tiles - 1) / tiles;
@@ -65,12 +68,17 @@ int pat_nn_conv3x3(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t l
   if (P > (int64_t)1 << 31 || (int64_t)B * H > INT32_MAX) return PAT_EINVAL;
   ConvArgs a{x, w, bias, y, mask, B, H, W, cin, cout, ldx, ldy, ldm, relu ? 1 : 0, accumulate ? 1 : 0};
   hipStream_t st = as_stream(stream);
+  // block tiles (pixels x output channels): 256 x 32, 256 x 64 or 128 x 128; a wave
+  // holds up to 4 x 4 accumulator tiles, so each operand load feeds up to 4 MFMAs
   if (cout <= 32) {
-    dim3 grid((unsigned)((P + 127) / 128), (unsigned)((cout + 31) / 32));
-    hipLaunchKernelGGL((k_conv3x3<4, 1>), grid, dim3(256), 0, st, a);
+    dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 31) / 32));
+    hipLaunchKernelGGL((k_conv3x3<4, 2, 4>), grid, dim3(256), 0, st, a);
+  } else if (cout % 128 != 0 && cout % 64 == 0) {
+    dim3 grid((unsigned)((P + 255) / 256), (unsigned)(cout / 64));
+    hipLaunchKernelGGL((k_conv3x3<4, 4, 4>), grid, dim3(256), 0, st, a);
   } else {
-    dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
-    hipLaunchKernelGGL((k_conv3x3<2, 2>), grid, dim3(256), 0, st, a);
+    dim3 grid((unsigned)((P + 127) / 128), (unsigned)((cout + 127) / 128));
+    hipLaunchKernelGGL((k_conv3x3<4, 4, 2>), grid, dim3(256), 0, st, a);
   }
   return launched();
 }
@@ -104,7 +112,11 @@ int pat_nn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int
   float* partb = part + (size_t)s.nsplit * cout * 9 * cin;
   WgradArgs a{x, dy, part, partb, B, H, W, cin, cout, ldx, ldy, s.per};
   hipStream_t st = as_stream(stream);
-  hipLaunchKernelGGL(k_wgrad, dim3((unsigned)s.ntiles, (unsigned)s.cotiles, (unsigned)s.nsplit), dim3(256), 0, st, a);
+  const dim3 grid((unsigned)s.ntiles, (unsigned)s.cotiles, (unsigned)s.nsplit);
+  if (s.ct == 32)
+    hipLaunchKernelGGL((k_wgrad<32>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, st, a);
   const int64_t nw = (int64_t)cout * 9 * cin;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(nn_blocks(nw + cout)), dim3(256), 0, st, (int)s.nsplit, nw, cout, part,
                      partb, dw, db);

@@ -59,17 +59,18 @@ struct ConvArgs {
   int relu, accum;
 };
 
-// Block: 4 waves in a 2 x 2 arrangement; a wave owns WM x WN MFMA tiles
-// (16 pixels x 16 output channels each).  Block tile: 32 WM pixels x 32 WN
-// output channels.
-template <int WM, int WN>
+// Block: 4 waves, BM along the pixels and 4 / BM along the output channels; a
+// wave owns WM x WN MFMA tiles (16 pixels x 16 output channels each).  Block
+// tile: 16 WM BM pixels x 16 WN (4 / BM) output channels.
+template <int WM, int WN, int BM>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+  constexpr int BN = 4 / BM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % BM, wn = wave / BM;
   const int r = lane & 15, kg = lane >> 4;
   const int64_t P = (int64_t)a.B * a.H * a.W;
-  const int64_t m0 = (int64_t)blockIdx.x * (32 * WM) + wm * (16 * WM);
-  const int n0 = blockIdx.y * (32 * WN) + wn * (16 * WN);
+  const int64_t m0 = (int64_t)blockIdx.x * (16 * WM * BM) + wm * (16 * WM);
+  const int n0 = blockIdx.y * (16 * WN * BN) + wn * (16 * WN);
   const int ktot = 9 * a.cin;
 
   int pb[WM], py[WM], px[WM];
@@ -183,8 +184,10 @@ __global__ void k_flip(int cout, int cin, const uint16_t* __restrict__ w, uint16
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient: block = 64 output channels x 64 (tap, ci) columns, pixel
+// Weight gradient: block = CT output channels x NT (tap, ci) columns, pixel
 // chunks of 64 staged (transposed) through LDS; grid.z splits the pixels.
+// CT = 64: waves 2 x 2, NT = 64; CT = 32 (32-channel layers): waves 1 x 4,
+// NT = 128.  Each wave owns 32 x 32 of the output (2 x 2 MFMA tiles).
 // ---------------------------------------------------------------------------
 struct WgradArgs {
   const uint16_t* x;    // [P][ldx] layer input slice (cin)
@@ -198,14 +201,24 @@ struct WgradArgs {
 constexpr int WG_CHUNK = 64;
 constexpr int WG_PAD = WG_CHUNK + 8;   // LDS row length (elements): 144 B rows stay 16-B aligned
 
+template <int CT>
+struct WgradTile {
+  static constexpr int WCO = CT / 32;          // waves along the output channels
+  static constexpr int WNN = 4 / WCO;          // waves along the (tap, ci) columns
+  static constexpr int NT = 32 * WNN;          // columns per block
+};
+
+template <int CT>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[64][WG_PAD];   // [co][pixel]
-  __shared__ __attribute__((aligned(16))) uint16_t sB[64][WG_PAD];   // [(tap, ci)][pixel]
+  constexpr int NT = WgradTile<CT>::NT, WCO = WgradTile<CT>::WCO;
+  constexpr int GA = CT / 8, GB = NT / 8;      // 8-value groups per pixel of each operand
+  __shared__ __attribute__((aligned(16))) uint16_t sA[CT][WG_PAD];   // [co][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[NT][WG_PAD];   // [(tap, ci)][pixel]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WCO, wn = wave / WCO;
   const int r = lane & 15, kg = lane >> 4;
   const int ktot = 9 * a.cin;
-  const int n0 = blockIdx.x * 64, co0 = blockIdx.y * 64;
+  const int n0 = blockIdx.x * NT, co0 = blockIdx.y * CT;
   const int64_t P = (int64_t)a.B * a.H * a.W;
   const int64_t nchunks = (P + WG_CHUNK - 1) / WG_CHUNK;
   const int64_t c_begin = blockIdx.z * a.chunks_per_split;
@@ -222,15 +235,21 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
 
   for (int64_t c = c_begin; c < c_end; ++c) {
     const int64_t pbase = c * WG_CHUNK;
+    // dY: 8 output channels of one pixel per group
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int g = tid + 256 * s;       // 512 groups of 8 values per operand
-      const int pl = g >> 3, grp = g & 7;
+    for (int g = tid; g < WG_CHUNK * GA; g += 256) {
+      const int pl = g / GA, grp = g % GA;
       const int64_t p = pbase + pl;
-      // dY: 8 output channels of one pixel
       const int co = co0 + 8 * grp;
       const u16x8 vd = (p < P && co < a.cout) ? load8(a.dy + p * a.ldy + co) : zero8;
-      // X: 8 input channels of one tap of one pixel
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sA[8 * grp + e][pl] = vd[e];
+    }
+    // X: 8 input channels of one tap of one pixel per group
+#pragma unroll
+    for (int g = tid; g < WG_CHUNK * GB; g += 256) {
+      const int pl = g / GB, grp = g % GB;
+      const int64_t p = pbase + pl;
       const int n = n0 + 8 * grp;
       u16x8 vx = zero8;
       if (p < P && n < ktot) {
@@ -244,13 +263,10 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
           vx = load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + ci);
       }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        sA[8 * grp + e][pl] = vd[e];
-        sB[8 * grp + e][pl] = vx[e];
-      }
+      for (int e = 0; e < 8; ++e) sB[8 * grp + e][pl] = vx[e];
     }
     __syncthreads();
-    if (bias_block && tid < 64)
+    if (bias_block && tid < CT)
       for (int q = 0; q < WG_CHUNK; ++q) bsum += bf2f(sA[tid][q]);
 #pragma unroll
     for (int ks = 0; ks < WG_CHUNK / 32; ++ks) {
@@ -281,7 +297,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         if (co < a.cout) part[(int64_t)co * ktot + n] = acc[i][j][q];
       }
   }
-  if (bias_block && tid < 64 && co0 + tid < a.cout) a.partb[(int64_t)blockIdx.z * a.cout + co0 + tid] = bsum;
+  if (bias_block && tid < CT && co0 + tid < a.cout) a.partb[(int64_t)blockIdx.z * a.cout + co0 + tid] = bsum;
 }
 
 // dw[e] = sum_s part[s][e] (e over cout * 9 cin), db[o] = sum_s partb[s][o]; fixed order.
