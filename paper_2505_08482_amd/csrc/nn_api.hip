@@ -29,10 +29,11 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // pixel-split of the weight gradient: enough blocks to fill the chip, whole chunks per split
 struct WgradSplit {
   int ct, ntiles, cotiles;
-  int64_t nchunks, per, nsplit;
+  int64_t nchunks, per, nsplit, ngroups;
 };
 
-// output-channel tile 32 for layers of at most 32 channels (128 columns per block), else 64 (64 columns)
+// output-channel tile 32 for layers of at most 32 channels (128 columns per block), else 64 (64 columns);
+// enough pixel splits to fill the chip, at least 16 chunks of 64 pixels per split
 WgradSplit wgrad_split(int64_t P, int cin, int cout) {
   WgradSplit s;
   s.ct = cout <= 32 ? 32 : 64;
@@ -42,14 +43,18 @@ WgradSplit wgrad_split(int64_t P, int cin, int cout) {
   s.nchunks = (P + WG_CHUNK - 1) / WG_CHUNK;
   const int64_t tiles = (int64_t)s.ntiles * s.cotiles;
   int64_t want = (2048 + tiles - 1) / tiles;
+  want = std::min<int64_t>(want, (s.nchunks + 15) / 16);
   want = std::max<int64_t>(1, std::min<int64_t>(want, s.nchunks));
   s.per = (s.nchunks + want - 1) / want;
   s.nsplit = (s.nchunks + s.per - 1) / s.per;
+  s.ngroups = (s.nsplit + WG_GROUP - 1) / WG_GROUP;
   return s;
 }
 
+// scratch: partials [nsplit][cout * 9 cin], bias partials [nsplit][cout], group sums [ngroups][cout * 9 cin + cout]
 size_t wgrad_bytes(const WgradSplit& s, int cin, int cout) {
-  return (size_t)s.nsplit * ((size_t)cout * 9 * cin + cout) * sizeof(float);
+  const size_t row = (size_t)cout * 9 * cin + cout;
+  return ((size_t)s.nsplit + (size_t)s.ngroups) * row * sizeof(float);
 }
 
 }  // namespace
@@ -118,8 +123,11 @@ int pat_nn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int
   else
     hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, st, a);
   const int64_t nw = (int64_t)cout * 9 * cin;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nn_blocks(nw + cout)), dim3(256), 0, st, (int)s.nsplit, nw, cout, part,
-                     partb, dw, db);
+  float* part2 = partb + (size_t)s.nsplit * cout;
+  hipLaunchKernelGGL(k_wgrad_reduce1, dim3((unsigned)((nw + cout + 255) / 256), (unsigned)s.ngroups), dim3(256), 0,
+                     st, (int)s.nsplit, nw, cout, part, partb, part2);
+  hipLaunchKernelGGL(k_wgrad_reduce2, dim3(nn_blocks(nw + cout)), dim3(256), 0, st, (int)s.ngroups, nw, cout, part2,
+                     dw, db);
   return launched();
 }
 

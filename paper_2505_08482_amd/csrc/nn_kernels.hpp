@@ -13,7 +13,7 @@
 //    kernel is the data gradient of a convolution when given the flipped
 //    weights (k_flip) and the gradient of the layer above.
 //  * k_wgrad: dW[o][(t,c)] = sum_p dY[p][o] X[p + offset_t][c] with the pixel
-//    sum split over blocks (partials reduced in a fixed order, k_wgrad_reduce).
+//    sum split over blocks (partials reduced in a fixed order, k_wgrad_reduce1/2).
 // MFMA operand layout (16x16x32): lane l supplies row (l mod 16) of A and
 // column (l mod 16) of B, each with 8 consecutive k; the accumulator holds
 // D[4 (l / 16) + r][l mod 16], r = 0..3.  The k order inside a step only has
@@ -185,7 +185,8 @@ __global__ void k_flip(int cout, int cin, const uint16_t* __restrict__ w, uint16
 
 // ---------------------------------------------------------------------------
 // Weight gradient: block = CT output channels x NT (tap, ci) columns, pixel
-// chunks of 64 staged (transposed) through LDS; grid.z splits the pixels.
+// chunks of 64 staged (transposed, 8 x 8 tiles in registers) through LDS;
+// grid.z splits the pixels.
 // CT = 64: waves 2 x 2, NT = 64; CT = 32 (32-channel layers): waves 1 x 4,
 // NT = 128.  Each wave owns 32 x 32 of the output (2 x 2 MFMA tiles).
 // ---------------------------------------------------------------------------
@@ -211,7 +212,6 @@ struct WgradTile {
 template <int CT>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   constexpr int NT = WgradTile<CT>::NT, WCO = WgradTile<CT>::WCO;
-  constexpr int GA = CT / 8, GB = NT / 8;      // 8-value groups per pixel of each operand
   __shared__ __attribute__((aligned(16))) uint16_t sA[CT][WG_PAD];   // [co][pixel]
   __shared__ __attribute__((aligned(16))) uint16_t sB[NT][WG_PAD];   // [(tap, ci)][pixel]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -235,39 +235,62 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
 
   for (int64_t c = c_begin; c < c_end; ++c) {
     const int64_t pbase = c * WG_CHUNK;
-    // dY: 8 output channels of one pixel per group
+    // Staging in 8 x 8 tiles: a thread loads 8 consecutive pixels x 8 channels
+    // (eight 16-byte loads), transposes them in registers and writes each
+    // channel's 8 pixels as one 16-byte LDS segment.  dY tiles: tid < CT;
+    // shifted-input tiles: CT <= tid < CT + NT.  Tile t: channel group t / 8,
+    // pixel block t % 8 of the chunk.
+    if (tid < CT + NT) {
+      const bool is_dy = tid < CT;
+      const int t = is_dy ? tid : tid - CT;
+      const int grp = t >> 3, pb = t & 7;
+      const int64_t p0 = pbase + 8 * pb;
+      u16x8 v[8];
+      if (is_dy) {
+        const int co = co0 + 8 * grp;
 #pragma unroll
-    for (int g = tid; g < WG_CHUNK * GA; g += 256) {
-      const int pl = g / GA, grp = g % GA;
-      const int64_t p = pbase + pl;
-      const int co = co0 + 8 * grp;
-      const u16x8 vd = (p < P && co < a.cout) ? load8(a.dy + p * a.ldy + co) : zero8;
+        for (int e = 0; e < 8; ++e)
+          v[e] = (p0 + e < P && co < a.cout) ? load8(a.dy + (p0 + e) * a.ldy + co) : zero8;
+      } else {
+        const int n = n0 + 8 * grp;
+        const bool nv = n < ktot && p0 < P;
+        const int tap = nv ? n / a.cin : 0, ci = n - tap * a.cin;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        // decode the first pixel once, then step along the row with carries
+        int xx = nv ? (int)(p0 % a.W) : 0;
+        const int64_t t0 = nv ? p0 / a.W : 0;
+        int yy = (int)(t0 % a.H), bb = (int)(t0 / a.H);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) sA[8 * grp + e][pl] = vd[e];
-    }
-    // X: 8 input channels of one tap of one pixel per group
-#pragma unroll
-    for (int g = tid; g < WG_CHUNK * GB; g += 256) {
-      const int pl = g / GB, grp = g % GB;
-      const int64_t p = pbase + pl;
-      const int n = n0 + 8 * grp;
-      u16x8 vx = zero8;
-      if (p < P && n < ktot) {
-        const int tap = n / a.cin, ci = n - tap * a.cin;
-        const int xx0 = (int)(p % a.W);
-        const int64_t t = p / a.W;
-        const int yy0 = (int)(t % a.H);
-        const int b = (int)(t / a.H);
-        const int yy = yy0 + tap / 3 - 1, xx = xx0 + tap % 3 - 1;
-        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-          vx = load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + ci);
+        for (int e = 0; e < 8; ++e) {
+          const int ys = yy + dy, xs = xx + dx;
+          const bool ok = nv && p0 + e < P && ys >= 0 && ys < a.H && xs >= 0 && xs < a.W;
+          v[e] = ok ? load8(a.x + ((int64_t)(bb * a.H + ys) * a.W + xs) * a.ldx + ci) : zero8;
+          if (++xx == a.W) {
+            xx = 0;
+            if (++yy == a.H) {
+              yy = 0;
+              ++bb;
+            }
+          }
+        }
       }
+      uint16_t(*dst)[WG_PAD] = is_dy ? sA : sB;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) sB[8 * grp + e][pl] = vx[e];
+      for (int ch = 0; ch < 8; ++ch) {
+        u16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = v[e][ch];
+        *reinterpret_cast<u16x8*>(&dst[8 * grp + ch][8 * pb]) = o;
+      }
     }
     __syncthreads();
     if (bias_block && tid < CT)
-      for (int q = 0; q < WG_CHUNK; ++q) bsum += bf2f(sA[tid][q]);
+#pragma unroll
+      for (int q = 0; q < WG_CHUNK / 8; ++q) {
+        const u16x8 v = *reinterpret_cast<const u16x8*>(&sA[tid][8 * q]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum += bf2f(v[e]);
+      }
 #pragma unroll
     for (int ks = 0; ks < WG_CHUNK / 32; ++ks) {
       bf16x8 A[2], Bv[2];
@@ -300,20 +323,35 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   if (bias_block && tid < CT && co0 + tid < a.cout) a.partb[(int64_t)blockIdx.z * a.cout + co0 + tid] = bsum;
 }
 
-// dw[e] = sum_s part[s][e] (e over cout * 9 cin), db[o] = sum_s partb[s][o]; fixed order.
-__global__ void k_wgrad_reduce(int nsplit, int64_t nw, int cout, const float* __restrict__ part,
-                               const float* __restrict__ partb, float* __restrict__ dw, float* __restrict__ db) {
+// Two-stage fixed-order reduction of the pixel-split partials.  Stage 1:
+// group g of WG_GROUP consecutive splits, part2[g][e] = sum over the group of
+// part[s][e] (e < nw) or partb[s][e - nw] (the bias columns).  Stage 2:
+// dw[e] / db[e - nw] = sum over the groups.
+constexpr int WG_GROUP = 32;
+
+__global__ void k_wgrad_reduce1(int nsplit, int64_t nw, int cout, const float* __restrict__ part,
+                                const float* __restrict__ partb, float* __restrict__ part2) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nw + cout) return;
+  const int s0 = blockIdx.y * WG_GROUP;
+  const int s1 = s0 + WG_GROUP < nsplit ? s0 + WG_GROUP : nsplit;
+  float s = 0.f;
+  if (e < nw) {
+    for (int z = s0; z < s1; ++z) s += part[(int64_t)z * nw + e];
+  } else {
+    for (int z = s0; z < s1; ++z) s += partb[(int64_t)z * cout + (e - nw)];
+  }
+  part2[(int64_t)blockIdx.y * (nw + cout) + e] = s;
+}
+
+__global__ void k_wgrad_reduce2(int ngroups, int64_t nw, int cout, const float* __restrict__ part2,
+                                float* __restrict__ dw, float* __restrict__ db) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nw + cout;
        e += (int64_t)gridDim.x * blockDim.x) {
     float s = 0.f;
-    if (e < nw) {
-      for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * nw + e];
-      dw[e] = s;
-    } else if (db) {
-      const int o = (int)(e - nw);
-      for (int z = 0; z < nsplit; ++z) s += partb[(int64_t)z * cout + o];
-      db[o] = s;
-    }
+    for (int g = 0; g < ngroups; ++g) s += part2[(int64_t)g * (nw + cout) + e];
+    if (e < nw) dw[e] = s;
+    else if (db) db[e - nw] = s;
   }
 }
 

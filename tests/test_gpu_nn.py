@@ -129,6 +129,7 @@ WGRAD_CASES = [
     (1, 24, 24, 64, 128, (64, 192), (0, 128)),  # input is a slice of a concatenation
     (1, 16, 16, 384, 128, (0, 384), (0, 128)),  # the network's widest layer
     (2, 8, 8, 256, 256, (0, 256), (64, 384)),   # the bottom layer, gradient a slice
+    (4, 128, 128, 8, 32, (0, 8), (0, 32)),      # 64 pixel splits: two groups of the two-stage reduction
 ]
 
 
