@@ -74,7 +74,20 @@ int pat_nn_conv3x3(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t l
   ConvArgs a{x, w, bias, y, mask, B, H, W, cin, cout, ldx, ldy, ldm, relu ? 1 : 0, accumulate ? 1 : 0};
   hipStream_t st = as_stream(stream);
   // block tiles (pixels x output channels): 256 x 32, 256 x 64 or 128 x 128; a wave
-  // holds up to 4 x 4 accumulator tiles, so each operand load feeds up to 4 MFMAs
+  // holds up to 4 x 4 accumulator tiles, so each operand load feeds up to 4 MFMAs.
+  // Rows of 64-pixel multiples with 32-channel multiples stage their input in LDS.
+  const int bm = cout <= 32 || (cout % 128 != 0 && cout % 64 == 0) ? 4 : 2;
+  if (cin % 32 == 0 && W % 64 == 0 && H % bm == 0) {
+    const unsigned nblk = (unsigned)((int64_t)B * (H / bm) * (W / 64));
+    if (cout <= 32) {
+      hipLaunchKernelGGL((k_conv3x3_rows<2, 4>), dim3(nblk, (unsigned)((cout + 31) / 32)), dim3(256), 0, st, a);
+    } else if (bm == 4) {
+      hipLaunchKernelGGL((k_conv3x3_rows<4, 4>), dim3(nblk, (unsigned)(cout / 64)), dim3(256), 0, st, a);
+    } else {
+      hipLaunchKernelGGL((k_conv3x3_rows<4, 2>), dim3(nblk, (unsigned)((cout + 127) / 128)), dim3(256), 0, st, a);
+    }
+    return launched();
+  }
   if (cout <= 32) {
     dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 31) / 32));
     hipLaunchKernelGGL((k_conv3x3<4, 2, 4>), grid, dim3(256), 0, st, a);

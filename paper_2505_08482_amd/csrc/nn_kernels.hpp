@@ -171,6 +171,93 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
   }
 }
 
+// Row-tiled variant for cin % 32 == 0, W % 64 == 0 and H % BM == 0: a block
+// covers BM image rows x 64 pixels (wave row wm = image row y0 + wm, its 4 MFMA
+// pixel tiles = 64 consecutive pixels) x 16 WN (4 / BM) output channels.  Per
+// 32-channel chunk the block stages its input rows with a one-pixel halo in LDS
+// once; every tap then reads its operand from LDS, so the input is fetched
+// once per chunk instead of once per tap.
+constexpr int ROWS_HALO_W = 66;
+
+template <int WN, int BM>
+__global__ __launch_bounds__(256) void k_conv3x3_rows(ConvArgs a) {
+  constexpr int BN = 4 / BM, HR = BM + 2;
+  __shared__ __attribute__((aligned(16))) uint16_t sX[HR][ROWS_HALO_W][32];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % BM, wn = wave / BM;
+  const int r = lane & 15, kg = lane >> 4;
+  const int tiles_x = a.W / 64, tiles_y = a.H / BM;
+  int bid = blockIdx.x;
+  const int tx = bid % tiles_x;
+  bid /= tiles_x;
+  const int ty = bid % tiles_y;
+  const int b = bid / tiles_y;
+  const int x0 = tx * 64, y0 = ty * BM;
+  const int n0 = blockIdx.y * (16 * WN * BN) + wn * (16 * WN);
+  const int ktot = 9 * a.cin;
+  const uint16_t* wrow[WN];
+  bool cv[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int co = n0 + 16 * j + r;
+    cv[j] = co < a.cout;
+    wrow[j] = a.w + (size_t)(cv[j] ? co : 0) * ktot + 8 * kg;
+  }
+  f32x4 acc[4][WN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  for (int c0 = 0; c0 < a.cin; c0 += 32) {
+    for (int g = threadIdx.x; g < HR * ROWS_HALO_W * 4; g += 256) {
+      const int row = g / (ROWS_HALO_W * 4), rem = g - row * (ROWS_HALO_W * 4);
+      const int px = rem >> 2, q = rem & 3;
+      const int yy = y0 - 1 + row, xx = x0 - 1 + px;
+      const bool ok = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+      const u16x8 v = ok ? load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + c0 + 8 * q) : zero8;
+      *reinterpret_cast<u16x8*>(&sX[row][px][8 * q]) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ty3 = tap / 3, tx3 = tap % 3;     // offsets (dy + 1, dx + 1) into the halo tile
+      bf16x8 A[4], Bv[WN];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        A[i] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sX[wm + ty3][16 * i + r + tx3][8 * kg]));
+#pragma unroll
+      for (int j = 0; j < WN; ++j) Bv[j] = as_bf16x8(cv[j] ? load8(wrow[j] + tap * a.cin + c0) : zero8);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  const int64_t prow = ((int64_t)b * a.H + y0 + wm) * a.W + x0;
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int co = n0 + 16 * j + r;
+    if (co >= a.cout) continue;
+    const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t p = prow + 16 * i + 4 * kg + q;
+        float v = acc[i][j][q] + bias;
+        if (a.relu) v = fmaxf(v, 0.f);
+        uint16_t* dst = a.y + p * a.ldy + co;
+        if (a.accum) v += bf2f(*dst);
+        if (a.mask && !(bf2f(a.mask[p * a.ldm + co]) > 0.f)) v = 0.f;
+        *dst = f2bf(v);
+      }
+  }
+}
+
 // Weights of the transposed convolution: wt[ci][t][co] = w[co][8 - t][ci]
 // (tap 8 - t is the opposite offset).
 __global__ void k_flip(int cout, int cin, const uint16_t* __restrict__ w, uint16_t* __restrict__ wt) {

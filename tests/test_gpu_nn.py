@@ -70,6 +70,11 @@ CONV_CASES = [
     (3, 8, 8, 128, 256, (0, 128), (0, 256)),
     (1, 16, 16, 384, 128, (0, 384), (0, 128)),  # the network's widest layer (decoder, 128^2 level)
     (1, 8, 8, 256, 256, (0, 256), (0, 256)),    # the bottom layer
+    # row-tiled kernel (W a multiple of 64, 32-channel chunks staged with their halo in LDS)
+    (2, 8, 64, 32, 32, (0, 32), (0, 32)),       # 4 rows x 64 pixels x 32 channels per block
+    (1, 12, 128, 64, 64, (32, 96), (0, 64)),    # 4 rows x 64 pixels x 64 channels, input a slice
+    (1, 6, 64, 96, 96, (0, 96), (16, 128)),     # 2 rows x 64 pixels x 128 channels (partial), output a slice
+    (1, 4, 64, 384, 128, (0, 384), (0, 128)),   # 12 channel chunks
 ]
 
 
@@ -95,7 +100,7 @@ def test_conv_forward_matches_oracle(case):
     assert np.all(got[..., outside] == 7.0)
 
 
-@pytest.mark.parametrize("case", CONV_CASES[:4])
+@pytest.mark.parametrize("case", CONV_CASES[:4] + [(2, 8, 64, 32, 64, None, None), (1, 4, 128, 128, 96, None, None)])
 def test_conv_data_gradient_matches_oracle(case):
     """Flipped weights + mask (+ accumulate) give dx = [mask > 0] (old + A^T dy)."""
     B, H, W, cin, cout, _, _ = case
