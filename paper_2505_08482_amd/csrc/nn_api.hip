@@ -210,8 +210,7 @@ int pat_nn_head_backward(int64_t P, int32_t C, const uint16_t* x, int32_t ldx, c
   float* part = static_cast<float*>(scratch);
   hipLaunchKernelGGL(k_head_bwd_dx, dim3(nn_blocks(P)), dim3(256), 0, st, P, C, x, ldx, w, dr, dx, lddx);
   hipLaunchKernelGGL(k_head_wgrad, dim3(HEAD_BLOCKS), dim3(256), 0, st, P, C, x, ldx, dr, part);
-  hipLaunchKernelGGL(k_head_wgrad_final, dim3(1), dim3(((C + 1 + 63) / 64) * 64), 0, st, HEAD_BLOCKS, C, part, dw,
-                     db);
+  hipLaunchKernelGGL(k_head_wgrad_final, dim3(C + 1), dim3(256), 0, st, HEAD_BLOCKS, C, part, dw, db);
   return launched();
 }
 

@@ -572,7 +572,7 @@ __global__ void k_head_bwd_dx(int64_t P, int C, const uint16_t* __restrict__ x, 
 
 // part[blk][c] = sum over the block's pixels of dr[p] x[p][c]; part[blk][C] = sum dr.
 // 256 threads, C divides 256: thread t owns channel t mod C and pixel lane t / C.
-constexpr int HEAD_BLOCKS = 256;
+constexpr int HEAD_BLOCKS = 2048;
 __global__ __launch_bounds__(256) void k_head_wgrad(int64_t P, int C, const uint16_t* __restrict__ x, int ldx,
                                                     const float* __restrict__ dr, float* __restrict__ part) {
   __shared__ float sh[256];
@@ -601,14 +601,24 @@ __global__ __launch_bounds__(256) void k_head_wgrad(int64_t P, int C, const uint
   }
 }
 
-__global__ void k_head_wgrad_final(int nblk, int C, const float* __restrict__ part, float* __restrict__ dw,
-                                   float* __restrict__ db) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > C) return;
+// Block c (0..C) sums column c of the partials: thread t adds blocks t, t + 256, ...
+// in order, then a fixed tree over the 256 threads.
+__global__ __launch_bounds__(256) void k_head_wgrad_final(int nblk, int C, const float* __restrict__ part,
+                                                          float* __restrict__ dw, float* __restrict__ db) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x;
   float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * (C + 1) + c];
-  if (c < C) dw[c] = s;
-  else db[0] = s;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(int64_t)b * (C + 1) + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (c < C) dw[c] = sh[0];
+    else db[0] = sh[0];
+  }
 }
 
 // Masked squared loss over B images sharing one mask [HW]:

@@ -31,6 +31,11 @@ def test_stored_weights_have_the_table_shapes():
     with np.load(learned.DEFAULT_WEIGHTS, allow_pickle=False) as f:
         base, cin = int(f["base"][0]), int(f["cin"][0])
         for name, ci, co in learned.layer_table(cin, base):
-            assert f[name + ".w"].shape == (co, 9, ci) and f[name + ".b"].shape == (co,)
-            assert np.all(np.isfinite(f[name + ".w"]))
+            w = f[name + ".w"]
+            assert w.shape == (co, 9, ci) and f[name + ".b"].shape == (co,)
+            if w.dtype == np.uint16:                   # bfloat16 bit patterns
+                w = (w.astype(np.uint32) << 16).view(np.float32)
+            assert np.all(np.isfinite(w))
+            # trained from He-normal initialisation (std sqrt(2 / (9 cin))): the scale stays of that order
+            assert 0.1 < w.std() / np.sqrt(2.0 / (9 * ci)) < 10.0, name
         assert f["head.w"].shape == (base,) and f["head.b"].shape == (1,)
