@@ -13,7 +13,7 @@ Conventions
   and every multigrid level covers the same physical square ``n * dx``.
 * Sensor positions are physical coordinates in metres, ``[m][2]`` = ``(x, y)``.
 * The time step follows CFL 0.3 at a fixed reference speed ``c_ref`` (Table 1's
-  steps are 0.3 * dz / 1580 m/s; this build uses c_ref = 1600 m/s, the upper end
+  steps are 0.3 * dz / 1580 m/s; here c_ref = 1600 m/s, the upper end
   of every configured sound-speed range).
 """
 from __future__ import annotations
@@ -167,7 +167,7 @@ PAPER_DURATION = 21.15e-6   # s, the common time span Nt * dt of Table 1's grids
 
 
 def paper_grid(name: str) -> Grid:
-    """FFT grid of a Table 1 row; the time step follows this build's CFL rule
+    """FFT grid of a Table 1 row; the time step follows the CFL rule above
     (c_ref = 1600 m/s) over the table's common duration."""
     dz, nz, ns, npml = TABLE1[name]
     n = nz + 2 * npml + (0 if name == "data" else 2 * ns)
@@ -202,7 +202,7 @@ def nine_disc_phantom(grid: Grid, K: int = 4, background: float = 1430.0, inclus
     (radius 1.5 mm, on a 3 x 3 lattice of pitch 6 mm) at ``inclusion`` in a
     ``background`` medium, and K initial pressures, each three discs (radius
     1 mm, ``p0_value`` Pa) at seeded positions inside the target square
-    (dataset k uses ``seed + k``).  The layout is this build's, drawn
+    (dataset k uses ``seed + k``).  The layout is a stand-in, drawn
     analytically on ``grid`` (a pixel belongs to a disc if its centre does)."""
     X, Y = np.meshgrid(pixel_centres(grid.nx) * grid.dx, pixel_centres(grid.ny) * grid.dx)
     c = np.full((grid.ny, grid.nx), background)

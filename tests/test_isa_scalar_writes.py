@@ -1,7 +1,7 @@
 """The gfx950 device code of the library performs no memory writes through the
 scalar data cache (scalar stores, scalar atomics, scalar-cache write-back):
 every store is a vector memory instruction.  Checked on the assembly that
-hipcc produces for this build (CPU only; needs hipcc)."""
+hipcc produces for the library (CPU only; needs hipcc)."""
 import os
 import re
 import shutil
