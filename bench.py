@@ -521,6 +521,8 @@ def main() -> int:
                          ("batch", lambda: batch_w3(args.batch_evals)),
                          ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters)),
                          ("paper_geometry", lambda: paper_geometry(args.tts_iters)),
+                         ("network", lambda: __import__("paper_2505_08482_amd.learned", fromlist=["x"])
+                          .time_network(4, 5)),
                          ("learned_start", lambda: learned_start(range(args.learned_cases))
                           if args.learned_cases > 0 else {"skipped": True})):
             progress(f"{name} ...")

@@ -582,6 +582,21 @@ def network_flops(net: UNet, B: int, H: int, W: int) -> Tuple[float, float]:
     return fwd, fwd + bwd
 
 
+def network_roofline_ms(net: UNet, B: int, H: int, W: int, mfma_tflops: float = 2500.0,
+                        hbm_gbs: float = 8000.0) -> float:
+    """Lower bound of the forward convolutions: per layer the larger of its
+    flops at the dense bf16 MFMA peak and its bf16 input + output + weight
+    bytes at the HBM peak, summed over the layers (milliseconds)."""
+    t = 0.0
+    for name, ci, co in net.table:
+        lvl = int(name[1])
+        P = B * (H >> lvl) * (W >> lvl)
+        f = 2.0 * P * 9 * ci * co
+        by = 2.0 * (P * (ci + co) + co * 9 * ci)
+        t += max(f / (mfma_tflops * 1e12), by / (hbm_gbs * 1e9))
+    return 1e3 * t
+
+
 def time_network(B: int = 4, steps: int = 5, H: int = FINE_N, W: int = FINE_N) -> Dict:
     """Average wall time of the forward pass and of one training step (forward,
     loss, backward, Adam) on random inputs, and the convolution flop rates."""
@@ -613,7 +628,9 @@ def time_network(B: int = 4, steps: int = 5, H: int = FINE_N, W: int = FINE_N) -
     torch.cuda.synchronize()
     ts = (time.perf_counter() - t0) / steps
     ff, ft = network_flops(net, B, H, W)
+    roof = network_roofline_ms(net, B, H, W)
     return {"batch": B, "size": [H, W], "forward_ms": round(1e3 * tf, 3), "train_step_ms": round(1e3 * ts, 3),
+            "forward_roofline_ms": round(roof, 4), "forward_roofline_frac": round(roof / (1e3 * tf), 3),
             "forward_conv_TFLOPs": round(ff / tf / 1e12, 1), "train_conv_TFLOPs": round(ft / ts / 1e12, 1),
             "forward_GFLOP": round(ff / 1e9, 2), "train_GFLOP": round(ft / 1e9, 2)}
 
