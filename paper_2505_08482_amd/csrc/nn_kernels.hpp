@@ -176,13 +176,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 // pixel tiles = 64 consecutive pixels) x 16 WN (4 / BM) output channels.  Per
 // 32-channel chunk the block stages its input rows with a one-pixel halo in LDS
 // once; every tap then reads its operand from LDS, so the input is fetched
-// once per chunk instead of once per tap.
+// once per chunk instead of once per tap.  The weights of each row of 3 taps
+// are staged beside it, so both MFMA operands come from LDS.
 constexpr int ROWS_HALO_W = 66;
 
 template <int WN, int BM>
 __global__ __launch_bounds__(256) void k_conv3x3_rows(ConvArgs a) {
-  constexpr int BN = 4 / BM, HR = BM + 2;
+  constexpr int BN = 4 / BM, HR = BM + 2, CT = 16 * WN * BN;
   __shared__ __attribute__((aligned(16))) uint16_t sX[HR][ROWS_HALO_W][32];
+  __shared__ __attribute__((aligned(16))) uint16_t sW[3][CT][32];   // one row of 3 taps of the chunk
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % BM, wn = wave / BM;
   const int r = lane & 15, kg = lane >> 4;
@@ -193,16 +195,9 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(ConvArgs a) {
   const int ty = bid % tiles_y;
   const int b = bid / tiles_y;
   const int x0 = tx * 64, y0 = ty * BM;
-  const int n0 = blockIdx.y * (16 * WN * BN) + wn * (16 * WN);
+  const int cb0 = blockIdx.y * CT;
+  const int nl = wn * (16 * WN);                  // the wave's first channel inside the block tile
   const int ktot = 9 * a.cin;
-  const uint16_t* wrow[WN];
-  bool cv[WN];
-#pragma unroll
-  for (int j = 0; j < WN; ++j) {
-    const int co = n0 + 16 * j + r;
-    cv[j] = co < a.cout;
-    wrow[j] = a.w + (size_t)(cv[j] ? co : 0) * ktot + 8 * kg;
-  }
   f32x4 acc[4][WN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -219,28 +214,39 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(ConvArgs a) {
       const u16x8 v = ok ? load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + c0 + 8 * q) : zero8;
       *reinterpret_cast<u16x8*>(&sX[row][px][8 * q]) = v;
     }
-    __syncthreads();
+    for (int ty3 = 0; ty3 < 3; ++ty3) {
+      // weights of taps 3 ty3 .. 3 ty3 + 2 for the block's channels, this chunk
+      for (int g = threadIdx.x; g < 3 * CT * 4; g += 256) {
+        const int t3 = g / (CT * 4), rem = g - t3 * (CT * 4);
+        const int col = rem >> 2, q = rem & 3;
+        const int co = cb0 + col;
+        const u16x8 v =
+            co < a.cout ? load8(a.w + (size_t)co * ktot + (3 * ty3 + t3) * a.cin + c0 + 8 * q) : zero8;
+        *reinterpret_cast<u16x8*>(&sW[t3][col][8 * q]) = v;
+      }
+      __syncthreads();
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int ty3 = tap / 3, tx3 = tap % 3;     // offsets (dy + 1, dx + 1) into the halo tile
-      bf16x8 A[4], Bv[WN];
+      for (int tx3 = 0; tx3 < 3; ++tx3) {          // offsets (dy + 1, dx + 1) into the halo tile
+        bf16x8 A[4], Bv[WN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        A[i] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sX[wm + ty3][16 * i + r + tx3][8 * kg]));
+        for (int i = 0; i < 4; ++i)
+          A[i] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sX[wm + ty3][16 * i + r + tx3][8 * kg]));
 #pragma unroll
-      for (int j = 0; j < WN; ++j) Bv[j] = as_bf16x8(cv[j] ? load8(wrow[j] + tap * a.cin + c0) : zero8);
+        for (int j = 0; j < WN; ++j)
+          Bv[j] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sW[tx3][nl + 16 * j + r][8 * kg]));
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
+          for (int j = 0; j < WN; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   const int64_t prow = ((int64_t)b * a.H + y0 + wm) * a.W + x0;
 #pragma unroll
   for (int j = 0; j < WN; ++j) {
-    const int co = n0 + 16 * j + r;
+    const int co = cb0 + nl + 16 * j + r;
     if (co >= a.cout) continue;
     const float bias = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
