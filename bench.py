@@ -348,6 +348,14 @@ def time_to_solution(wl_fine, c_true, y_fine, w, iters: int, target: float = 2.0
                         "E_c_last": round(lv.E_c[-1], 3) if lv.E_c else None} for lv in out["levels"]]}
 
 
+def network_timing():
+    """The learned start's network at the fine-level size (512^2, batch 4):
+    forward and training-step times, convolution flop rates, and the forward
+    against the sum over its layers of max(flops / MFMA peak, bytes / HBM peak)."""
+    from paper_2505_08482_amd import learned
+    return learned.time_network(4, 5)
+
+
 def learned_start(cases, fine_iters: int = 20, targets=(2.0, 1.0)):
     """Held-out phantoms (the 256^2 workload's generators at 512^2, K = 8,
     seeds 5000 + case): plain multigrid 128 -> 256 -> 512 against the coarse
@@ -521,8 +529,7 @@ def main() -> int:
                          ("batch", lambda: batch_w3(args.batch_evals)),
                          ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters)),
                          ("paper_geometry", lambda: paper_geometry(args.tts_iters)),
-                         ("network", lambda: __import__("paper_2505_08482_amd.learned", fromlist=["x"])
-                          .time_network(4, 5)),
+                         ("network", network_timing),
                          ("learned_start", lambda: learned_start(range(args.learned_cases))
                           if args.learned_cases > 0 else {"skipped": True})):
             progress(f"{name} ...")
