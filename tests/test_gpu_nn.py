@@ -384,3 +384,47 @@ def test_training_steps_reduce_the_loss():
         net.adam(3e-3)
     print(f"[nn] training loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
     assert np.all(np.isfinite(losses)) and losses[-1] < 0.7 * losses[0]
+
+
+def test_degenerate_shapes():
+    """A single-pixel image (only the centre tap sees data), one output channel
+    (a 16-wide MFMA tile with 15 idle columns), a one-pixel weight gradient,
+    2 x 2 pooling to one pixel, and a loss mask with no pixel in it."""
+    announce("nn degenerate shapes")
+    rng = np.random.default_rng(99)
+    x, x64 = bf(rng.standard_normal((1, 1, 1, 8)))
+    w, w64 = bf(rng.standard_normal((1, 9, 8)))
+    b, b64 = f32([0.25])
+    y = torch.zeros((1, 1, 1, 1), dtype=torch.bfloat16, device="cuda")
+    nn.conv3x3(x, w, b, y)
+    # weight gradient over one pixel: only the centre tap is non-zero
+    dy, dy64 = bf(rng.standard_normal((1, 1, 1, 8)))
+    dw = torch.full((8, 9, 8), 7.0, dtype=torch.float32, device="cuda")
+    db = torch.zeros(8, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(nn.wgrad_scratch_bytes(1, 1, 1, 8, 8), dtype=torch.uint8, device="cuda")
+    nn.conv3x3_wgrad(x, dy, dw, db, scratch)
+    # 2 x 2 -> 1 x 1 pooling and back
+    xp, xp64 = bf(rng.standard_normal((1, 2, 2, 8)))
+    yp = torch.empty((1, 1, 1, 8), dtype=torch.bfloat16, device="cuda")
+    nn.avgpool2(xp, yp)
+    up = torch.empty((1, 2, 2, 8), dtype=torch.bfloat16, device="cuda")
+    nn.upsample2(yp, up)
+    # empty loss mask
+    r, _ = f32(rng.standard_normal((2, 4, 4)))
+    t, _ = f32(rng.standard_normal((2, 4, 4)))
+    mask = torch.zeros((4, 4), dtype=torch.uint8, device="cuda")
+    dr = torch.full((2, 4, 4), 3.0, dtype=torch.float32, device="cuda")
+    out = torch.full((2,), 5.0, dtype=torch.float64, device="cuda")
+    nn.masked_mse(r, t, mask, dr, out, torch.empty(nn.mse_scratch_bytes(), dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    ref = U.conv3x3(x64, w64, b64)
+    assert_close(back(y), ref, U.conv3x3(np.abs(x64), np.abs(w64), np.abs(b64)), what="1-pixel conv")
+    assert abs(float(back(y)[0, 0, 0, 0]) - (float(w64[0, 4] @ x64[0, 0, 0]) + 0.25)) <= 2.0 ** -8 * abs(ref).max() + 1e-6
+    _, ref_w, ref_b = U.conv3x3_backward(x64, np.zeros((8, 9, 8)), dy64)
+    got_w = dw.cpu().numpy().astype(np.float64)
+    assert np.all(got_w[:, [0, 1, 2, 3, 5, 6, 7, 8], :] == 0.0)
+    assert np.allclose(got_w, ref_w, rtol=1e-6, atol=1e-6) and np.allclose(db.cpu().numpy(), ref_b, rtol=1e-6)
+    assert_close(back(yp), U.avgpool2(xp64), U.avgpool2(np.abs(xp64)), what="2x2 pool")
+    assert np.array_equal(back(up), U.upsample2(back(yp)))
+    assert float(out[0].item()) == 0.0 and float(out[1].item()) == 0.0
+    assert np.all(dr.cpu().numpy() == 0.0)
