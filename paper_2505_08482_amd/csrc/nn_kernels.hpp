@@ -205,26 +205,72 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(ConvArgs a) {
     for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
 
-  for (int c0 = 0; c0 < a.cin; c0 += 32) {
-    for (int g = threadIdx.x; g < HR * ROWS_HALO_W * 4; g += 256) {
-      const int row = g / (ROWS_HALO_W * 4), rem = g - row * (ROWS_HALO_W * 4);
-      const int px = rem >> 2, q = rem & 3;
-      const int yy = y0 - 1 + row, xx = x0 - 1 + px;
-      const bool ok = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-      const u16x8 v = ok ? load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + c0 + 8 * q) : zero8;
-      *reinterpret_cast<u16x8*>(&sX[row][px][8 * q]) = v;
-    }
-    for (int ty3 = 0; ty3 < 3; ++ty3) {
-      // weights of taps 3 ty3 .. 3 ty3 + 2 for the block's channels, this chunk
-      for (int g = threadIdx.x; g < 3 * CT * 4; g += 256) {
-        const int t3 = g / (CT * 4), rem = g - t3 * (CT * 4);
-        const int col = rem >> 2, q = rem & 3;
-        const int co = cb0 + col;
-        const u16x8 v =
-            co < a.cout ? load8(a.w + (size_t)co * ktot + (3 * ty3 + t3) * a.cin + c0 + 8 * q) : zero8;
-        *reinterpret_cast<u16x8*>(&sW[t3][col][8 * q]) = v;
+  // Staging through registers: the global loads of the next stage (the next
+  // tap row's weights, or the next chunk's input rows) are issued right after
+  // a barrier, so they are in flight while the current stage's MFMAs run.
+  constexpr int XG = HR * ROWS_HALO_W * 4, WG = 3 * CT * 4;        // 16-byte groups per stage
+  constexpr int NXG = (XG + 255) / 256, NWG = (WG + 255) / 256;    // per thread
+  u16x8 rx[NXG], rw[NWG];
+  auto load_x = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < NXG; ++k) {
+      const int g = threadIdx.x + 256 * k;
+      rx[k] = zero8;
+      if (g < XG) {
+        const int row = g / (ROWS_HALO_W * 4), rem = g - row * (ROWS_HALO_W * 4);
+        const int px = rem >> 2, q = rem & 3;
+        const int yy = y0 - 1 + row, xx = x0 - 1 + px;
+        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          rx[k] = load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + c0 + 8 * q);
       }
+    }
+  };
+  auto store_x = [&]() {
+#pragma unroll
+    for (int k = 0; k < NXG; ++k) {
+      const int g = threadIdx.x + 256 * k;
+      if (g < XG) {
+        const int row = g / (ROWS_HALO_W * 4), rem = g - row * (ROWS_HALO_W * 4);
+        *reinterpret_cast<u16x8*>(&sX[row][rem >> 2][8 * (rem & 3)]) = rx[k];
+      }
+    }
+  };
+  auto load_w = [&](int c0, int ty3) {        // weights of taps 3 ty3 .. 3 ty3 + 2, this chunk
+#pragma unroll
+    for (int k = 0; k < NWG; ++k) {
+      const int g = threadIdx.x + 256 * k;
+      rw[k] = zero8;
+      if (g < WG) {
+        const int t3 = g / (CT * 4), rem = g - t3 * (CT * 4);
+        const int co = cb0 + (rem >> 2), q = rem & 3;
+        if (co < a.cout) rw[k] = load8(a.w + (size_t)co * ktot + (3 * ty3 + t3) * a.cin + c0 + 8 * q);
+      }
+    }
+  };
+  auto store_w = [&]() {
+#pragma unroll
+    for (int k = 0; k < NWG; ++k) {
+      const int g = threadIdx.x + 256 * k;
+      if (g < WG) {
+        const int t3 = g / (CT * 4), rem = g - t3 * (CT * 4);
+        *reinterpret_cast<u16x8*>(&sW[t3][rem >> 2][8 * (rem & 3)]) = rw[k];
+      }
+    }
+  };
+
+  load_x(0);
+  load_w(0, 0);
+  for (int c0 = 0; c0 < a.cin; c0 += 32) {
+    store_x();
+    for (int ty3 = 0; ty3 < 3; ++ty3) {
+      store_w();
       __syncthreads();
+      if (ty3 < 2) {
+        load_w(c0, ty3 + 1);
+      } else if (c0 + 32 < a.cin) {
+        load_w(c0 + 32, 0);
+        load_x(c0 + 32);
+      }
 #pragma unroll
       for (int tx3 = 0; tx3 < 3; ++tx3) {          // offsets (dy + 1, dx + 1) into the halo tile
         bf16x8 A[4], Bv[WN];
