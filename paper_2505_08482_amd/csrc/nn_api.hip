@@ -32,12 +32,12 @@ struct WgradSplit {
   int64_t nchunks, per, nsplit, ngroups;
 };
 
-// output-channel tile 32 for layers of at most 32 channels (128 columns per block), else 64 (64 columns);
+// output-channel tile 32, 64 or 128 (at most 32, 64, or more channels), 128 (tap, ci) columns per block;
 // enough pixel splits to fill the chip, at least 16 chunks of 64 pixels per split
 WgradSplit wgrad_split(int64_t P, int cin, int cout) {
   WgradSplit s;
-  s.ct = cout <= 32 ? 32 : 64;
-  const int nt = s.ct == 32 ? WgradTile<32>::NT : WgradTile<64>::NT;
+  s.ct = cout <= 32 ? 32 : cout <= 64 ? 64 : 128;
+  const int nt = 128;
   s.ntiles = (9 * cin + nt - 1) / nt;
   s.cotiles = (cout + s.ct - 1) / s.ct;
   s.nchunks = (P + WG_CHUNK - 1) / WG_CHUNK;
@@ -132,9 +132,11 @@ int pat_nn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int
   hipStream_t st = as_stream(stream);
   const dim3 grid((unsigned)s.ntiles, (unsigned)s.cotiles, (unsigned)s.nsplit);
   if (s.ct == 32)
-    hipLaunchKernelGGL((k_wgrad<32>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_wgrad<32, 128>), grid, dim3(256), 0, st, a);
+  else if (s.ct == 64)
+    hipLaunchKernelGGL((k_wgrad<64, 128>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_wgrad<128, 128>), grid, dim3(256), 0, st, a);
   const int64_t nw = (int64_t)cout * 9 * cin;
   float* part2 = partb + (size_t)s.nsplit * cout;
   hipLaunchKernelGGL(k_wgrad_reduce1, dim3((unsigned)((nw + cout + 255) / 256), (unsigned)s.ngroups), dim3(256), 0,

@@ -326,8 +326,9 @@ __global__ void k_flip(int cout, int cin, const uint16_t* __restrict__ w, uint16
 // Weight gradient: block = CT output channels x NT (tap, ci) columns, pixel
 // chunks of 64 staged (transposed, 8 x 8 tiles in registers) through LDS;
 // grid.z splits the pixels.
-// CT = 64: waves 2 x 2, NT = 64; CT = 32 (32-channel layers): waves 1 x 4,
-// NT = 128.  Each wave owns 32 x 32 of the output (2 x 2 MFMA tiles).
+// Tiles (CT x NT): 32 x 128 for layers of at most 32 channels (waves 1 x 4,
+// 2 x 2 MFMA tiles each), 64 x 128 for 64 channels (waves 2 x 2, 2 x 4 tiles),
+// 128 x 128 otherwise (waves 2 x 2, 4 x 4 tiles).
 // ---------------------------------------------------------------------------
 struct WgradArgs {
   const uint16_t* x;    // [P][ldx] layer input slice (cin)
@@ -341,16 +342,21 @@ struct WgradArgs {
 constexpr int WG_CHUNK = 64;
 constexpr int WG_PAD = WG_CHUNK + 8;   // LDS row length (elements): 144 B rows stay 16-B aligned
 
-template <int CT>
+// Block tile CT output channels x NT columns, waves WCO x (4 / WCO); a wave owns
+// (CT / WCO) x (NT / (4 / WCO)) of the output as MI x NJ MFMA tiles.
+template <int CT, int NT>
 struct WgradTile {
-  static constexpr int WCO = CT / 32;          // waves along the output channels
-  static constexpr int WNN = 4 / WCO;          // waves along the (tap, ci) columns
-  static constexpr int NT = 32 * WNN;          // columns per block
+  static constexpr int WCO = CT >= 64 ? 2 : 1;   // waves along the output channels
+  static constexpr int WNN = 4 / WCO;            // waves along the (tap, ci) columns
+  static constexpr int TM = CT / WCO, TN = NT / WNN;
+  static constexpr int MI = TM / 16, NJ = TN / 16;
+  static_assert(CT + NT <= 256, "one staging tile per thread");
 };
 
-template <int CT>
+template <int CT, int NT>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
-  constexpr int NT = WgradTile<CT>::NT, WCO = WgradTile<CT>::WCO;
+  using Tl = WgradTile<CT, NT>;
+  constexpr int WCO = Tl::WCO, TM = Tl::TM, TN = Tl::TN, MI = Tl::MI, NJ = Tl::NJ;
   __shared__ __attribute__((aligned(16))) uint16_t sA[CT][WG_PAD];   // [co][pixel]
   __shared__ __attribute__((aligned(16))) uint16_t sB[NT][WG_PAD];   // [(tap, ci)][pixel]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -365,11 +371,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   const bool bias_block = blockIdx.x == 0;
   const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
 
-  f32x4 acc[2][2];
+  f32x4 acc[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
 
   for (int64_t c = c_begin; c < c_end; ++c) {
@@ -432,30 +438,30 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       }
 #pragma unroll
     for (int ks = 0; ks < WG_CHUNK / 32; ++ks) {
-      bf16x8 A[2], Bv[2];
+      bf16x8 A[MI], Bv[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        A[i] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sA[32 * wm + 16 * i + r][32 * ks + 8 * kg]));
+      for (int i = 0; i < MI; ++i)
+        A[i] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sA[TM * wm + 16 * i + r][32 * ks + 8 * kg]));
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        Bv[j] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sB[32 * wn + 16 * j + r][32 * ks + 8 * kg]));
+      for (int j = 0; j < NJ; ++j)
+        Bv[j] = as_bf16x8(*reinterpret_cast<const u16x8*>(&sB[TN * wn + 16 * j + r][32 * ks + 8 * kg]));
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
+        for (int j = 0; j < NJ; ++j) acc[i][j] = mfma(A[i], Bv[j], acc[i][j]);
     }
     __syncthreads();
   }
   float* part = a.part + (int64_t)blockIdx.z * a.cout * ktot;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int n = n0 + 32 * wn + 16 * j + r;
+  for (int j = 0; j < NJ; ++j) {
+    const int n = n0 + TN * wn + 16 * j + r;
     if (n >= ktot) continue;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int co = co0 + 32 * wm + 16 * i + 4 * kg + q;
+        const int co = co0 + TM * wm + 16 * i + 4 * kg + q;
         if (co < a.cout) part[(int64_t)co * ktot + n] = acc[i][j][q];
       }
   }
