@@ -9,9 +9,13 @@
 // Dense contractions run on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
 // accumulation):
 //  * k_conv3x3: implicit GEMM  Y[p][o] = sum_k A[p][k] Wt[o][k], k = (tap, ci),
-//    A[p][(t,c)] = X[p + offset_t][c] (zero outside the image).  The same
-//    kernel is the data gradient of a convolution when given the flipped
-//    weights (k_flip) and the gradient of the layer above.
+//    A[p][(t,c)] = X[p + offset_t][c] (zero outside the image), operands
+//    gathered straight from memory (any shape with cin % 8 == 0);
+//    k_conv3x3_rows: the same GEMM for rows of 64-pixel multiples and
+//    32-channel chunks, with the block's input rows (plus halo) and weights
+//    staged in LDS and the next stage prefetched into registers.  Both are
+//    the data gradient of a convolution when given the flipped weights
+//    (k_flip) and the gradient of the layer above.
 //  * k_wgrad: dW[o][(t,c)] = sum_p dY[p][o] X[p + offset_t][c] with the pixel
 //    sum split over blocks (partials reduced in a fixed order, k_wgrad_reduce1/2).
 // MFMA operand layout (16x16x32): lane l supplies row (l mod 16) of A and
