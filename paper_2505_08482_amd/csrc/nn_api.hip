@@ -28,17 +28,21 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // pixel-split of the weight gradient: enough blocks to fill the chip, whole chunks per split
 struct WgradSplit {
+  int rows;                // input channels per block of the halo-staged kernel (0: not used)
   int ct, ntiles, cotiles;
   int64_t nchunks, per, nsplit, ngroups;
 };
 
-// output-channel tile 32, 64 or 128 (at most 32, 64, or more channels), 128 (tap, ci) columns per block;
-// enough pixel splits to fill the chip, at least 16 chunks of 64 pixels per split
-WgradSplit wgrad_split(int64_t P, int cin, int cout) {
+// Layers of at most 32 output and 16 or 32 input channels on rows of 64-pixel
+// multiples use the halo-staged kernel (32 output x 16 input channels x 9 taps
+// per block; wider inputs re-stage dY per channel group and lose to the tiles); otherwise the output-channel tile is 32, 64 or 128 (at most
+// 32, 64, or more channels) with 128 (tap, ci) columns per block.  Enough pixel
+// splits to fill the chip, at least 16 chunks of 64 pixels per split.
+WgradSplit wgrad_split(int64_t P, int W, int cin, int cout) {
   WgradSplit s;
+  s.rows = cout <= 32 && W % 64 == 0 && cin % 16 == 0 && cin <= 32 ? 16 : 0;
   s.ct = cout <= 32 ? 32 : cout <= 64 ? 64 : 128;
-  const int nt = 128;
-  s.ntiles = (9 * cin + nt - 1) / nt;
+  s.ntiles = s.rows ? cin / s.rows : (9 * cin + 127) / 128;
   s.cotiles = (cout + s.ct - 1) / s.ct;
   s.nchunks = (P + WG_CHUNK - 1) / WG_CHUNK;
   const int64_t tiles = (int64_t)s.ntiles * s.cotiles;
@@ -110,7 +114,7 @@ int pat_nn_conv3x3_flip(int32_t cout, int32_t cin, const uint16_t* w, uint16_t* 
 
 int pat_nn_wgrad_scratch_bytes(int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout, size_t* bytes) {
   if (!bytes || B < 1 || H < 1 || W < 1 || cin < 8 || cout < 8) return PAT_EINVAL;
-  const WgradSplit s = wgrad_split((int64_t)B * H * W, cin, cout);
+  const WgradSplit s = wgrad_split((int64_t)B * H * W, W, cin, cout);
   *bytes = wgrad_bytes(s, cin, cout);
   return PAT_OK;
 }
@@ -124,14 +128,16 @@ int pat_nn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int
   if (!aligned16(x) || !aligned16(dy)) return PAT_EINVAL;
   const int64_t P = (int64_t)B * H * W;
   if (P > (int64_t)1 << 31) return PAT_EINVAL;
-  const WgradSplit s = wgrad_split(P, cin, cout);
+  const WgradSplit s = wgrad_split(P, W, cin, cout);
   if (scratch_bytes < wgrad_bytes(s, cin, cout)) return PAT_EWORKSPACE;
   float* part = static_cast<float*>(scratch);
   float* partb = part + (size_t)s.nsplit * cout * 9 * cin;
   WgradArgs a{x, dy, part, partb, B, H, W, cin, cout, ldx, ldy, s.per};
   hipStream_t st = as_stream(stream);
   const dim3 grid((unsigned)s.ntiles, (unsigned)s.cotiles, (unsigned)s.nsplit);
-  if (s.ct == 32)
+  if (s.rows == 16)
+    hipLaunchKernelGGL((k_wgrad_rows<16>), grid, dim3(256), 0, st, a);
+  else if (s.ct == 32)
     hipLaunchKernelGGL((k_wgrad<32, 128>), grid, dim3(256), 0, st, a);
   else if (s.ct == 64)
     hipLaunchKernelGGL((k_wgrad<64, 128>), grid, dim3(256), 0, st, a);

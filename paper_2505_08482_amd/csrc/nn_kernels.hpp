@@ -472,6 +472,121 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   if (bias_block && tid < CT && co0 + tid < a.cout) a.partb[(int64_t)blockIdx.z * a.cout + co0 + tid] = bsum;
 }
 
+// Weight gradient of layers with at most 32 output channels on rows of 64-pixel
+// multiples (cin a multiple of CI = 16 or 32): block = 32 output channels x CI
+// input channels x all 9 taps (9 CI columns).  A 64-pixel chunk lies in one image row;
+// its three input rows with a one-pixel halo are staged once (3 x 66 x 16),
+// and the 9 shifted copies are built from LDS as transposed 8 x 8 tiles, so the
+// input is fetched once per chunk and row instead of once per tap.  The
+// 2 x 9 CI / 16 MFMA tiles of the block are dealt round-robin to the 4 waves.
+template <int CI>
+__global__ __launch_bounds__(256) void k_wgrad_rows(WgradArgs a) {
+  constexpr int WGR_CI = CI, WGR_COLS = 9 * CI, WGR_TILES = 2 * WGR_COLS / 16;
+  constexpr int SLOTS = (WGR_TILES + 3) / 4, HG = CI / 8;
+  __shared__ __attribute__((aligned(16))) uint16_t sA[32][WG_PAD];          // [co][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[WGR_COLS][WG_PAD];    // [(tap, ci)][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sXh[3][66][WGR_CI];      // input rows with halo
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, kg = lane >> 4;
+  const int ktot = 9 * a.cin;
+  const int ci0 = blockIdx.x * WGR_CI, co0 = blockIdx.y * 32;
+  const int64_t nchunks = (int64_t)a.B * a.H * a.W / WG_CHUNK;
+  const int64_t c_begin = blockIdx.z * a.chunks_per_split;
+  const int64_t c_end = c_begin + a.chunks_per_split < nchunks ? c_begin + a.chunks_per_split : nchunks;
+  const bool bias_block = blockIdx.x == 0;
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  f32x4 acc[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+
+  for (int64_t c = c_begin; c < c_end; ++c) {
+    const int64_t p0 = c * WG_CHUNK;
+    const int x0 = (int)(p0 % a.W);
+    const int64_t t0 = p0 / a.W;
+    const int y = (int)(t0 % a.H), b = (int)(t0 / a.H);
+    // dY: 4 channel groups x 8 pixel blocks of 8 x 8, transposed in registers
+    if (tid < 32) {
+      const int grp = tid >> 3, pb = tid & 7;
+      const int co = co0 + 8 * grp;
+      u16x8 v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = co < a.cout ? load8(a.dy + (p0 + 8 * pb + e) * a.ldy + co) : zero8;
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        u16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = v[e][ch];
+        *reinterpret_cast<u16x8*>(&sA[8 * grp + ch][8 * pb]) = o;
+      }
+    }
+    // input rows y - 1 .. y + 1, pixels x0 - 1 .. x0 + 64, channels ci0 .. ci0 + CI - 1
+    for (int g = tid; g < 3 * 66 * HG; g += 256) {
+      const int row = g / (66 * HG), rem = g - row * (66 * HG);
+      const int px = rem / HG, h = rem % HG;
+      const int yy = y - 1 + row, xx = x0 - 1 + px;
+      const bool ok = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+      *reinterpret_cast<u16x8*>(&sXh[row][px][8 * h]) =
+          ok ? load8(a.x + ((int64_t)(b * a.H + yy) * a.W + xx) * a.ldx + ci0 + 8 * h) : zero8;
+    }
+    __syncthreads();
+    // the 9 shifted copies, transposed: tile (tap, channel group h, pixel block pb)
+    for (int g = tid; g < WGR_COLS; g += 256) {
+      const int tap = g / CI, rem = g % CI;
+      const int h = rem >> 3, pb = rem & 7;
+      const int dy = tap / 3, dx = tap % 3;
+      u16x8 v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = *reinterpret_cast<const u16x8*>(&sXh[dy][8 * pb + e + dx][8 * h]);
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        u16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = v[e][ch];
+        *reinterpret_cast<u16x8*>(&sB[CI * tap + 8 * h + ch][8 * pb]) = o;
+      }
+    }
+    __syncthreads();
+    if (bias_block && tid < 32)
+#pragma unroll
+      for (int q = 0; q < WG_CHUNK / 8; ++q) {
+        const u16x8 v = *reinterpret_cast<const u16x8*>(&sA[tid][8 * q]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum += bf2f(v[e]);
+      }
+#pragma unroll
+    for (int ks = 0; ks < WG_CHUNK / 32; ++ks) {
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        const int tt = wave + 4 * s;
+        if (tt < WGR_TILES) {
+          const int i = tt & 1, j = tt >> 1;
+          const bf16x8 A = as_bf16x8(*reinterpret_cast<const u16x8*>(&sA[16 * i + r][32 * ks + 8 * kg]));
+          const bf16x8 Bv = as_bf16x8(*reinterpret_cast<const u16x8*>(&sB[16 * j + r][32 * ks + 8 * kg]));
+          acc[s] = mfma(A, Bv, acc[s]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* part = a.part + (int64_t)blockIdx.z * a.cout * ktot;
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int tt = wave + 4 * s;
+    if (tt >= WGR_TILES) continue;
+    const int i = tt & 1, j = tt >> 1;
+    const int nl = 16 * j + r;                    // local column: tap nl / CI, channel nl % CI
+    const int n = (nl / CI) * a.cin + ci0 + (nl % CI);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co = co0 + 16 * i + 4 * kg + q;
+      if (co < a.cout) part[(int64_t)co * ktot + n] = acc[s][q];
+    }
+  }
+  if (bias_block && tid < 32 && co0 + tid < a.cout) a.partb[(int64_t)blockIdx.z * a.cout + co0 + tid] = bsum;
+}
+
 // Two-stage fixed-order reduction of the pixel-split partials.  Stage 1:
 // group g of WG_GROUP consecutive splits, part2[g][e] = sum over the group of
 // part[s][e] (e < nw) or partb[s][e - nw] (the bias columns).  Stage 2:

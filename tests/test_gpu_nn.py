@@ -135,6 +135,12 @@ WGRAD_CASES = [
     (1, 16, 16, 384, 128, (0, 384), (0, 128)),  # the network's widest layer
     (2, 8, 8, 256, 256, (0, 256), (64, 384)),   # the bottom layer, gradient a slice
     (4, 128, 128, 8, 32, (0, 8), (0, 32)),      # 64 pixel splits: two groups of the two-stage reduction
+    # halo-staged kernel (rows of 64-pixel multiples, at most 32 output and 16 or 32 input channels)
+    (2, 4, 64, 32, 32, (0, 32), (0, 32)),
+    (1, 6, 128, 32, 32, (32, 96), (32, 64)),    # input and gradient slices
+    (1, 3, 64, 16, 24, (16, 32), (0, 24)),      # 24 output channels (partial tile), input a slice
+    (1, 6, 128, 96, 32, (0, 96), (32, 64)),     # 96 input channels: the tiled kernel on the same rows
+    (4, 32, 128, 32, 32, (0, 32), (0, 32)),     # many pixel splits
 ]
 
 
