@@ -93,6 +93,15 @@ int pat_workspace_size(const pat_plan* plan, int32_t ckpt_every, size_t* bytes);
 int pat_forward(pat_plan* plan, const float* c, const float* p0, float* data,
                 void* ws, size_t ws_bytes, int32_t ckpt_every, int32_t record, void* stream);
 
+/* The recorded pressure field p^n (eq. (1) solved as in Sec. 2.1; n = 0 is
+ * p0) of all K datasets, [K][ny][nx] float32, inside a workspace that the last
+ * recording pat_forward of this plan filled with the whole history
+ * (ckpt_every = 0).  *field receives a DEVICE address inside ws (read-only,
+ * valid until the next pat_forward on that workspace); no work is enqueued.
+ * PAT_EINVAL for n outside [0, nt) or null arguments; PAT_EWORKSPACE if ws
+ * holds no store-all recording of this plan. */
+int pat_history_field(const pat_plan* plan, const void* ws, int32_t n, const float** field);
+
 /* Data term of eq. (4) with W_i = w[i] (w: DEVICE array of K weights 1/sigma_i):
  * resid = w^2 (data - y) (the adjoint source, eq. (6) with the sign folded
  * in) and J = 1/2 sum w^2 (data - y)^2 accumulated in float64 into the DEVICE

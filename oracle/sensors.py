@@ -1,5 +1,5 @@
-"""Point sensors (Sec. 2.2: the data are sampled at a discrete set of sensor
-locations).  TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+"""Point sensors (Sec. 2.2): each datum is the pressure read at one sensor
+position.  TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 Reading: the pressure at a sensor is the bilinear interpolation of the four
 surrounding cell centres; pixel ``i`` of an axis with ``n`` points sits at

@@ -39,9 +39,25 @@ def flags():
 
 
 def build(verbose: bool = True) -> str:
+    """Compile every source to an object in parallel (each is self-contained:
+    no device code crosses files), then link the shared library."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + ["-o", tmp] + [os.path.join(CSRC, f) for f in SOURCES]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    cflags = [f for f in flags() if f != "-shared"]
+    objs, procs = [], []
     t0 = time.time()
+    for f in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(f)[0] + ".o")
+        cmd = [hipcc()] + cflags + ["-c", "-o", obj, os.path.join(CSRC, f)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd, cwd=HERE), cmd))
+        objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)

@@ -1044,6 +1044,15 @@ int pat_forward(pat_plan* p, const float* c, const float* p0, float* data, void*
   return PAT_OK;
 }
 
+int pat_history_field(const pat_plan* p, const void* ws, int32_t n, const float** field) {
+  if (!p || !ws || !field || n < 0 || n >= p->g.nt) return PAT_EINVAL;
+  *field = nullptr;
+  if (!p->recorded || p->rec_ws != ws || p->rec_ckpt != 0) return PAT_EWORKSPACE;
+  const Layout L = make_layout(p, 0);
+  *field = at<const float>(const_cast<void*>(ws), L.hist + (size_t)n * L.F);
+  return PAT_OK;
+}
+
 int pat_misfit(pat_plan* p, const float* data, const float* y, const float* w, float* resid, double* J,
                void* stream) {
   if (!p || !data || !y || !w || !resid || !J) return PAT_EINVAL;

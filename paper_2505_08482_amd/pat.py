@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpat.so")
 PAT_OK, PAT_EINVAL, PAT_EUNSUPPORTED, PAT_EWORKSPACE, PAT_EHIP = 0, -1, -2, -3, -4
 
 EXPORTS = (
-    "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_misfit",
+    "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_history_field", "pat_misfit",
     "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_prolong_phys", "pat_time_interp",
     "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_dot", "pat_status_string",
     "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_batch_gradient",
@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
     L.pat_plan_destroy.argtypes = [vp]
     L.pat_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
     L.pat_forward.argtypes = [vp, vp, vp, vp, vp, sz, i32, i32, vp]
+    L.pat_history_field.argtypes = [vp, vp, i32, ctypes.POINTER(vp)]
     L.pat_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pat_adjoint_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.pat_project_update.argtypes = [i64, vp, vp, f32, vp, vp, f32, f32, vp]
@@ -189,6 +190,18 @@ class Plan:
         _check(lib().pat_forward(self._h, _f32(c, g.ny * g.nx, "c"), _f32(p0, self.K * g.ny * g.nx, "p0"),
                                  _f32(data, self.K * g.nt * self.m, "data"), _ptr(ws), ws.numel(),
                                  int(ckpt_every), 1 if record else 0, _stream()), "pat_forward")
+
+    def history_field(self, ws, n: int):
+        """The recorded pressure field p^n [K][ny][nx] of a store-all workspace,
+        as a device tensor view into ``ws`` (valid until the next forward)."""
+        import torch
+        ptr = ctypes.c_void_p()
+        _check(lib().pat_history_field(self._h, _ptr(ws), int(n), ctypes.byref(ptr)), "pat_history_field")
+        nbytes = self.K * self.grid.ny * self.grid.nx * 4
+        off = ptr.value - ws.data_ptr()
+        if off < 0 or off + nbytes > ws.numel():
+            raise PatError(PAT_EINVAL, "pat_history_field: address outside the workspace")
+        return ws[off:off + nbytes].view(torch.float32).view(self.field_shape)
 
     def misfit(self, data, y, w, resid, J):
         import torch

@@ -79,3 +79,59 @@ def observed_data(wl, c_true32, p032, noise_seed):
                               record=False)
     y, sigma = I.add_noise(clean, noise_seed)
     return y, 1.0 / sigma
+
+
+# Bars of the GPU (float32) vs oracle (float64) comparison.  Whole arrays:
+# sensor data rel-L2 <= 1e-4, gradients rel-L2 <= 1e-3.  Local checks beside
+# them, so that one wrong trace or one wrong band of pixels cannot hide under a
+# global norm: every sensor trace whose norm is at least a tenth of the rms
+# trace norm within 1e-3 of its own norm, and the largest gradient error
+# within 1e-3 of the largest gradient entry (observed float32 errors are
+# 1e-6..1e-5 of the whole-array norms, so both leave a factor of 100 or more).
+DATA_TOL = 1e-4
+GRAD_TOL = 1e-3
+TRACE_TOL = 1e-3
+MAXABS_TOL = 1e-3
+
+
+def trace_errors(gpu_data, ora_data):
+    """Per-trace relative errors ``|d_gpu - d_ora| / |d_ora|`` over time for the
+    traces ``[K][m]`` whose norm is at least 0.1 of the rms trace norm."""
+    a = np.asarray(gpu_data, dtype=np.float64)
+    b = np.asarray(ora_data, dtype=np.float64)
+    nb = np.sqrt(np.sum(b * b, axis=1))              # [K][m]
+    ne = np.sqrt(np.sum((a - b) ** 2, axis=1))
+    sel = nb >= 0.1 * np.sqrt(np.mean(nb * nb))
+    return ne[sel] / nb[sel]
+
+
+def max_ratio(a, b) -> float:
+    """``max |a - b| / max |b|``; for stacked fields ``[K][ny][nx]`` the largest
+    of the per-field ratios."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if b.ndim == 3:
+        return max(max_ratio(a[k], b[k]) for k in range(b.shape[0]))
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def check_parity(tag, gpu, ora, keys=("data", "g_p0", "g_c")):
+    """Assert the whole-array and the local bars for the given outputs; prints
+    every figure first (one line, flushed)."""
+    out = {}
+    if "data" in keys:
+        out["data"] = rel_l2(gpu["data"], ora["data"])
+        out["trace_max"] = float(np.max(trace_errors(gpu["data"], ora["data"])))
+    for k in ("g_p0", "g_c"):
+        if k in keys:
+            out[k] = rel_l2(gpu[k], ora[k])
+            out[k + "_max"] = max_ratio(gpu[k], ora[k])
+    print(f"[parity] {tag}: " + "  ".join(f"{k} {v:.2e}" for k, v in out.items()), flush=True)
+    if "data" in keys:
+        assert out["data"] <= DATA_TOL, (tag, out)
+        assert out["trace_max"] <= TRACE_TOL, (tag, out)
+    for k in ("g_p0", "g_c"):
+        if k in keys:
+            assert out[k] <= GRAD_TOL, (tag, out)
+            assert out[k + "_max"] <= MAXABS_TOL, (tag, out)
+    return out

@@ -5,9 +5,9 @@
 * a batch of K datasets gives bit-identical data and g_p0 to K single runs,
   and g_c equal to their sum up to float32 rounding (also for K not a
   multiple of the datasets per block of the adjoint density pass);
-* oracle parity at 512^2 on a short time axis, and the W1 launch
-  configuration (512^2, K = 8, 4000 samples) checked by properties that hold
-  at any size: linearity in p0 and the adjoint dot-product identity;
+* the W1 launch configuration (512^2, K = 8, 4000 samples) checked by
+  properties that hold at any size (linearity in p0, the adjoint dot-product
+  identity in p0) and against the oracle on one dataset, g_c included;
 * the generic (any radix) kernels and the power-of-two kernels agree.
 """
 import dataclasses
@@ -68,22 +68,6 @@ def test_batch_equals_single_runs_bitwise(K):
     assert rel_l2(full["g_c"], gc_sum) <= 1e-5
 
 
-def test_oracle_parity_512_short():
-    wl = I.w1(K=1, nt=400)
-    c_true, p0 = I.phantoms(wl, 3)
-    c_true = c_true.astype(np.float32)
-    p0 = p0.astype(np.float32)
-    y, w = observed_data(wl, c_true, p0, noise_seed=3500)
-    c = np.full_like(c_true, np.float32(1500.0))
-    announce("512 K=1 nt=400 oracle")
-    ora = oracle_forward_adjoint(wl, c, p0, y=y, w=w)
-    announce("512 K=1 nt=400 gpu")
-    gpu = gpu_forward_adjoint(wl, c, p0, resid32=ora["resid"].astype(np.float32))
-    e = (rel_l2(gpu["data"], ora["data"]), rel_l2(gpu["g_p0"], ora["g_p0"]), rel_l2(gpu["g_c"], ora["g_c"]))
-    print(f"[parity] 512 short: {e}", flush=True)
-    assert e[0] <= 1e-4 and e[1] <= 1e-3 and e[2] <= 1e-3
-
-
 def test_w1_full_size_properties():
     """512^2, K = 8, 4000 samples (the benchmark's launch configuration):
     f(a + 2b) = f(a) + 2 f(b) and <f(p0), y> = <p0, f^T y> in float32."""
@@ -126,29 +110,35 @@ def test_w1_full_size_properties():
 
 def test_w1_full_size_dataset_vs_oracle():
     """The benchmark's launch configuration itself (512^2, K = 8, 4000 samples,
-    the true heterogeneous c): dataset 0's sensor traces and g_p0 against the
-    float64 oracle run on that dataset alone (the datasets are independent given
-    c; g_c, a sum over all eight, is covered by the dot test above)."""
-    import torch
-    from paper_2505_08482_amd import pat
+    the true heterogeneous c) against the float64 oracle.  The adjoint source
+    is nonzero for dataset 5 only (the second dataset of the second group of
+    four in the grouped g_c reduction): the datasets are independent given c and
+    a zero residual gives a zero adjoint field, so g_c of the K = 8 launch must
+    equal the oracle's g_c of dataset 5 alone, g_p0 of the other datasets must
+    be exactly zero, and dataset 5's traces and g_p0 must match its oracle run."""
+    from gpu_helpers import check_parity
     wl = I.w1()
     g = wl.grid
+    j = 5
     c_np, p0_np = I.phantoms(wl, 3)
     c32 = c_np.astype(np.float32)
     p032 = p0_np.astype(np.float32)
     rng = np.random.default_rng(31)
-    r32 = rng.standard_normal((wl.K, g.nt, wl.m)).astype(np.float32)
+    r32 = np.zeros((wl.K, g.nt, wl.m), dtype=np.float32)
+    r32[j] = rng.standard_normal((g.nt, wl.m)).astype(np.float32)
     announce("w1 full size gpu K=8")
     gpu = gpu_forward_adjoint(wl, c32, p032, resid32=r32)
-    announce("w1 full size oracle dataset 0")
-    data, hist = kspace.forward(g, wl.sensors, c32.astype(np.float64), p032[:1].astype(np.float64))
-    gp0, _ = kspace.adjoint_gradient(g, wl.sensors, c32.astype(np.float64), p032[:1].astype(np.float64),
-                                     r32[:1].astype(np.float64), hist)
+    for k in range(wl.K):
+        if k != j:
+            assert not np.any(gpu["g_p0"][k]), k
+    announce(f"w1 full size oracle dataset {j}")
+    data, hist = kspace.forward(g, wl.sensors, c32.astype(np.float64), p032[j:j + 1].astype(np.float64))
+    gp0, gc = kspace.adjoint_gradient(g, wl.sensors, c32.astype(np.float64), p032[j:j + 1].astype(np.float64),
+                                      r32[j:j + 1].astype(np.float64), hist)
     del hist
-    e_d = rel_l2(gpu["data"][0], data[0])
-    e_p = rel_l2(gpu["g_p0"][0], gp0[0])
-    print(f"[w1 parity] data {e_d:.2e} g_p0 {e_p:.2e}", flush=True)
-    assert e_d <= 1e-4 and e_p <= 1e-3
+    check_parity(f"w1 full size, dataset {j}",
+                 {"data": gpu["data"][j:j + 1], "g_p0": gpu["g_p0"][j:j + 1], "g_c": gpu["g_c"]},
+                 {"data": data, "g_p0": gp0, "g_c": gc})
 
 
 def test_generic_and_power_of_two_kernels_agree():

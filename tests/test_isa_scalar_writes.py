@@ -18,11 +18,14 @@ FORBIDDEN = re.compile(
 
 @pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
                     reason="hipcc not available")
-def test_device_code_has_no_scalar_memory_writes(tmp_path):
-    out = tmp_path / "pat_device.s"
+@pytest.mark.parametrize("source", B.SOURCES)
+def test_device_code_has_no_scalar_memory_writes(tmp_path, source):
+    """Every source linked into the library (the wave solver and the MFMA
+    network kernels)."""
+    out = tmp_path / (source + ".s")
     flags = [f for f in B.flags() if f not in ("-shared", "-fPIC")]
     cmd = [B.hipcc()] + flags + ["--cuda-device-only", "-S", "-o", str(out),
-                                 os.path.join(B.CSRC, "pat_api.hip")]
+                                 os.path.join(B.CSRC, source)]
     subprocess.run(cmd, check=True, capture_output=True)
     asm = out.read_text()
     assert "v_" in asm and "global_store" in asm

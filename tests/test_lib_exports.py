@@ -58,6 +58,8 @@ def test_host_side_argument_checks():
     dummy = ctypes.c_void_p(1)
     assert L.pat_prolong_phys(1, dummy, 4, 4, 0.0, dummy, 8, 8, 5e-5, None) == pat.PAT_EINVAL
     assert L.pat_batch_gradient(0, None, 1, None) == pat.PAT_EINVAL
+    out = ctypes.c_void_p()
+    assert L.pat_history_field(None, dummy, 0, ctypes.byref(out)) == pat.PAT_EINVAL
     assert L.pat_batch_gradient(1, dummy, 17, None) == pat.PAT_EINVAL
     assert L.pat_trace_start(0) == pat.PAT_EINVAL
     assert L.pat_plan_set_tile(None, 0) == pat.PAT_EINVAL
