@@ -158,6 +158,20 @@ size_t pat_lbfgs_scratch_bytes(int32_t npairs);
 int pat_lbfgs_direction(int64_t n, const float* g, int32_t npairs, const float* const* s,
                         const float* const* y, float* d, void* scratch, void* stream);
 
+/* Alg. 1 as pat_lbfgs_direction, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): no scratch argument and no allocation of any kind; the
+ * library keeps the scratch in one static device array per GPU, sized for at
+ * most PAT_LBFGS_NOALLOC_MAX_PAIRS pairs (5.1 KB), held until the process
+ * ends.  Same arguments, results bit-identical to pat_lbfgs_direction.
+ * PAT_EUNSUPPORTED if npairs > PAT_LBFGS_NOALLOC_MAX_PAIRS; PAT_EINVAL as for
+ * pat_lbfgs_direction; PAT_EHIP if the array's device address cannot be
+ * obtained.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (different streams or host threads) race. */
+#define PAT_LBFGS_NOALLOC_MAX_PAIRS 64
+int pat_lbfgs_direction_noalloc(int64_t n, const float* g, int32_t npairs, const float* const* s,
+                                const float* const* y, float* d, void* stream);
+
 /* Float64 dot product a . b of n floats into the DEVICE scalar *out
  * (deterministic two-level reduction; `scratch` as for pat_lbfgs_direction
  * with npairs = 0). */

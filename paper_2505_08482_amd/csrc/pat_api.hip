@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1191,13 +1192,14 @@ int pat_dot(int64_t n, const float* a, const float* b, double* out, void* scratc
   return dot_into(static_cast<hipStream_t>(stream), n, a, b, static_cast<double*>(scratch), out);
 }
 
-int pat_lbfgs_direction(int64_t n, const float* g, int32_t np, const float* const* s, const float* const* y, float* d,
-                        void* scratch, void* stream) {
-  if (n <= 0 || !g || !d || np < 0 || !scratch || (np > 0 && (!s || !y))) return PAT_EINVAL;
-  for (int j = 0; j < np; ++j)
-    if (!s[j] || !y[j]) return PAT_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  double* partial = static_cast<double*>(scratch);
+}  // extern "C"
+
+namespace {
+
+// Alg. 1 on the stream, with `scr` holding pat_lbfgs_scratch_bytes(np) bytes.
+int lbfgs_two_loop(hipStream_t st, int64_t n, const float* g, int32_t np, const float* const* s,
+                   const float* const* y, float* d, double* scr) {
+  double* partial = scr;
   double* sc = partial + RED_BLOCKS;
   if (d != g) PAT_TRY(copy_dev(st, g, d, (size_t)n * sizeof(float)));
   if (np == 0) return PAT_OK;
@@ -1217,6 +1219,62 @@ int pat_lbfgs_direction(int64_t n, const float* g, int32_t np, const float* cons
     PAT_TRY(last_error());
   }
   return PAT_OK;
+}
+
+int lbfgs_args_ok(int64_t n, const float* g, int32_t np, const float* const* s, const float* const* y,
+                  const float* d) {
+  if (n <= 0 || !g || !d || np < 0 || (np > 0 && (!s || !y))) return PAT_EINVAL;
+  for (int j = 0; j < np; ++j)
+    if (!s[j] || !y[j]) return PAT_EINVAL;
+  return PAT_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Library-owned scratch of the allocation-free two-loop recursion: one static
+// device array (every GPU that runs the library holds its own copy for the
+// life of the process).  Host code never passes the array's name to a kernel:
+// its device address on the current GPU comes from hipGetSymbolAddress, taken
+// once per device and kept.
+// ----------------------------------------------------------------------------
+namespace noalloc {
+constexpr int kMaxDevices = 64;
+constexpr size_t kDoubles = RED_BLOCKS + 2 * PAT_LBFGS_NOALLOC_MAX_PAIRS + 2;
+static __device__ __align__(256) double scratch[kDoubles];
+std::mutex g_mu;
+double* g_addr[kMaxDevices] = {};
+
+int scratch_address(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PAT_EHIP;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!g_addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PAT_EHIP;
+    g_addr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_addr[dev];
+  return PAT_OK;
+}
+}  // namespace noalloc
+
+}  // namespace
+
+extern "C" {
+
+int pat_lbfgs_direction(int64_t n, const float* g, int32_t np, const float* const* s, const float* const* y, float* d,
+                        void* scratch, void* stream) {
+  PAT_TRY(lbfgs_args_ok(n, g, np, s, y, d));
+  if (!scratch) return PAT_EINVAL;
+  return lbfgs_two_loop(static_cast<hipStream_t>(stream), n, g, np, s, y, d, static_cast<double*>(scratch));
+}
+
+int pat_lbfgs_direction_noalloc(int64_t n, const float* g, int32_t np, const float* const* s,
+                                const float* const* y, float* d, void* stream) {
+  PAT_TRY(lbfgs_args_ok(n, g, np, s, y, d));
+  if (np > PAT_LBFGS_NOALLOC_MAX_PAIRS) return PAT_EUNSUPPORTED;
+  double* scr = nullptr;
+  PAT_TRY(noalloc::scratch_address(&scr));
+  return lbfgs_two_loop(static_cast<hipStream_t>(stream), n, g, np, s, y, d, scr);
 }
 
 int pat_plan_set_tile(pat_plan* p, int32_t col_tile) {

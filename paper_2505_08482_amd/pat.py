@@ -21,10 +21,12 @@ PAT_OK, PAT_EINVAL, PAT_EUNSUPPORTED, PAT_EWORKSPACE, PAT_EHIP = 0, -1, -2, -3, 
 EXPORTS = (
     "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_history_field", "pat_misfit",
     "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_prolong_phys", "pat_time_interp",
-    "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_dot", "pat_status_string",
+    "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_lbfgs_direction_noalloc", "pat_dot", "pat_status_string",
     "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_batch_gradient",
     "pat_ou_create", "pat_ou_destroy", "pat_ou_scratch_bytes", "pat_ou_apply", "pat_ou_prior",
 )
+
+LBFGS_NOALLOC_MAX_PAIRS = 64
 
 PASS_KINDS = ("fwd_col_grad", "fwd_row_u", "fwd_col_div", "fwd_row_rho",
               "adj_col_summ", "adj_row_rho", "adj_col_grad", "adj_row_u")
@@ -77,6 +79,7 @@ def lib() -> ctypes.CDLL:
     L.pat_lbfgs_scratch_bytes.argtypes = [i32]
     L.pat_lbfgs_scratch_bytes.restype = sz
     L.pat_lbfgs_direction.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp]
+    L.pat_lbfgs_direction_noalloc.argtypes = [i64, vp, i32, vp, vp, vp, vp]
     L.pat_dot.argtypes = [i64, vp, vp, vp, vp, vp]
     L.pat_trace_start.argtypes = [i32]
     L.pat_trace_stop.argtypes = []
@@ -270,6 +273,18 @@ def lbfgs_direction(g, s_list: Sequence, y_list: Sequence, d, scratch):
     _check(lib().pat_lbfgs_direction(n, _f32(g, n, "g"), npairs, ctypes.cast(S, ctypes.c_void_p),
                                      ctypes.cast(Y, ctypes.c_void_p), _f32(d, n, "d"), _ptr(scratch), _stream()),
            "pat_lbfgs_direction")
+
+
+def lbfgs_direction_noalloc(g, s_list: Sequence, y_list: Sequence, d):
+    """Alg. 1 without a scratch argument (the library's static per-GPU array;
+    at most PAT_LBFGS_NOALLOC_MAX_PAIRS pairs); bit-identical to lbfgs_direction."""
+    n = g.numel()
+    npairs = len(s_list)
+    S = (ctypes.c_void_p * max(npairs, 1))(*[_f32(s, n, "s") for s in s_list])
+    Y = (ctypes.c_void_p * max(npairs, 1))(*[_f32(y, n, "y") for y in y_list])
+    _check(lib().pat_lbfgs_direction_noalloc(n, _f32(g, n, "g"), npairs, ctypes.cast(S, ctypes.c_void_p),
+                                             ctypes.cast(Y, ctypes.c_void_p), _f32(d, n, "d"), _stream()),
+           "pat_lbfgs_direction_noalloc")
 
 
 def dot(a, b, out, scratch):
