@@ -791,7 +791,6 @@ template <int N, int MODE, int TC = Cfg<N>::TC>
 __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
                                                                 float2* __restrict__ SB, float scale,
                                                                 int32_t* __restrict__ step, int32_t delta) {
-  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;   // first pass of a step
   constexpr int T = Cfg<N>::T, P = LdsCol<N, TC>::P;
   static_assert((TC == 4 && P % 16 == 4) || (TC == 8 && P % 16 == 2) || (TC >= 16 && P % 2 == 1),
                 "column pitch");
@@ -825,11 +824,14 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
   float2 eyv[8];
   const float2 exv = ext[col0 ? 0 : (ok ? cx : 0)];
   const float2 exN = ext[nx / 2];
+  // every lane loads the Nyquist-column kappa too (used by the DC + i Nyquist
+  // column only): a load under a lane condition would be waited for inside
+  // its branch, serialising the prologue of the blocks that hold column 0
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     const int e = q + T * m;
     kap[m] = tb.kappa[(size_t)e * nh + (ok ? cx : 0)] * scale;
-    kapN[m] = col0 ? tb.kappa[(size_t)e * nh + nx / 2] * scale : 0.f;
+    kapN[m] = tb.kappa[(size_t)e * nh + nx / 2] * scale;
     eyv[m] = eyt[e];
   }
   float2* LL[2] = {LA + cl * P, LB + cl * P};
@@ -909,6 +911,10 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
       if (TWO_OUT) *at_byte(colB, o) = a[1][m];
     }
   }
+  // first pass of a step: advance the step counter (read by the row passes
+  // that follow, not by this one), after the stores so that no block waits
+  // for it before its own loads
+  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;
 }
 
 }  // namespace fast
