@@ -81,17 +81,30 @@ def conv3x3(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
     return y + b
 
 
+def conv3x3_data_gradient(w: np.ndarray, dy: np.ndarray) -> np.ndarray:
+    """``dx`` of ``sum(dy * conv3x3(x, w, b))``: y[p] gathers x[p + d], so
+    x[q] receives from y[q - d] through tap d."""
+    dx = np.zeros(dy.shape[:3] + (w.shape[2],))
+    for t, (di, dj) in enumerate(TAPS):
+        dx += _shift(dy @ w[:, t, :], -di, -dj)
+    return dx
+
+
+def conv3x3_weight_gradient(x: np.ndarray, dy: np.ndarray):
+    """``(dw, db)`` of ``sum(dy * conv3x3(x, w, b))``: the sum over pixels of
+    ``dy[p][o] x[p + d][c]`` for every tap d (one matrix product per tap)."""
+    cout, cin = dy.shape[-1], x.shape[-1]
+    dw = np.zeros((cout, 9, cin))
+    d2 = dy.reshape(-1, cout)
+    for t, (di, dj) in enumerate(TAPS):
+        dw[:, t, :] = d2.T @ _shift(x, di, dj).reshape(-1, cin)
+    return dw, dy.sum(axis=(0, 1, 2))
+
+
 def conv3x3_backward(x: np.ndarray, w: np.ndarray, dy: np.ndarray):
     """Gradients ``(dx, dw, db)`` of ``sum(dy * conv3x3(x, w, b))``."""
-    dx = np.zeros_like(x)
-    dw = np.zeros_like(w)
-    for t, (di, dj) in enumerate(TAPS):
-        xs = _shift(x, di, dj)
-        dw[:, t, :] = np.einsum("bijo,bijc->oc", dy, xs)
-        # y[p] gathers x[p + d]; so x[q] receives from y[q - d]
-        dx += _shift(dy @ w[:, t, :], -di, -dj)
-    db = dy.sum(axis=(0, 1, 2))
-    return dx, dw, db
+    dw, db = conv3x3_weight_gradient(x, dy)
+    return conv3x3_data_gradient(w, dy), dw, db
 
 
 def relu(v: np.ndarray) -> np.ndarray:

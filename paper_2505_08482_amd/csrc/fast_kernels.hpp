@@ -787,7 +787,11 @@ __global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* _
 // Column pass (transform length NY = N), nx/2 folded columns, TC per block
 // ===========================================================================
 // TC: columns per block (the default Cfg<N>::TC, or a width picked by the tuner).
-template <int N, int MODE, int TC = Cfg<N>::TC>
+// SEQ: the two transforms of a thread run one after the other (loads of the
+// first array issued first, so its transform starts while the second array's
+// loads land, and the first output is stored while the second is transformed)
+// instead of stage by stage together (shared barriers).  Same arithmetic.
+template <int N, int MODE, int TC = Cfg<N>::TC, bool SEQ = false>
 __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
                                                                 float2* __restrict__ SB, float scale,
                                                                 int32_t* __restrict__ step, int32_t delta) {
@@ -809,11 +813,20 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
   Fft<N> fft;
   fft.init(tb.tw_y, q);
   float2 a[2][8];
+  if (SEQ) {
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const unsigned o = lane_b + m * row_b;
-    a[0][m] = *at_byte(colA, o);
-    if (TWO_IN) a[1][m] = *at_byte(colB, o);
+    for (int m = 0; m < 8; ++m) a[0][m] = *at_byte(colA, lane_b + m * row_b);
+    if (TWO_IN) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) a[1][m] = *at_byte(colB, lane_b + m * row_b);
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const unsigned o = lane_b + m * row_b;
+      a[0][m] = *at_byte(colA, o);
+      if (TWO_IN) a[1][m] = *at_byte(colB, o);
+    }
   }
   // spectral multiplier factors (prefetched before the transforms)
   constexpr bool PLUS = MODE == COL_GRAD1 || MODE == COL_PAIRP;
@@ -835,10 +848,14 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
     eyv[m] = eyt[e];
   }
   float2* LL[2] = {LA + cl * P, LB + cl * P};
-  if (TWO_IN)
+  if (TWO_IN && SEQ) {
+    fft.template run<-1, 1>(&a[0], &LL[0], q);
+    fft.template run<-1, 1>(&a[1], &LL[1], q);
+  } else if (TWO_IN) {
     fft.template run<-1, 2>(a, LL, q);
-  else
+  } else {
     fft.template run<-1, 1>(a, LL, q);
+  }
   if (c0 == 0) {
     // column 0 holds DC + i Nyquist: split by conjugate symmetry along y
     __syncthreads();
@@ -899,16 +916,29 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
       }
     }
   }
-  if (TWO_OUT)
-    fft.template run<+1, 2>(a, LL, q);
-  else
-    fft.template run<+1, 1>(a, LL, q);
-  if (ok) {
+  if (TWO_OUT && SEQ) {
+    fft.template run<+1, 1>(&a[0], &LL[0], q);
+    if (ok) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const unsigned o = lane_b + m * row_b;
-      *at_byte(colA, o) = a[0][m];
-      if (TWO_OUT) *at_byte(colB, o) = a[1][m];
+      for (int m = 0; m < 8; ++m) *at_byte(colA, lane_b + m * row_b) = a[0][m];
+    }
+    fft.template run<+1, 1>(&a[1], &LL[1], q);
+    if (ok) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) *at_byte(colB, lane_b + m * row_b) = a[1][m];
+    }
+  } else {
+    if (TWO_OUT)
+      fft.template run<+1, 2>(a, LL, q);
+    else
+      fft.template run<+1, 1>(a, LL, q);
+    if (ok) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const unsigned o = lane_b + m * row_b;
+        *at_byte(colA, o) = a[0][m];
+        if (TWO_OUT) *at_byte(colB, o) = a[1][m];
+      }
     }
   }
   // first pass of a step: advance the step counter (read by the row passes

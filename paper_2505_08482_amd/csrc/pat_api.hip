@@ -96,6 +96,7 @@ struct pat_plan {
   int K = 0, m = 0, nh = 0;
   bool fast = false;         // register-resident power-of-two passes (folded spectra)
   int col_tile = 0;          // column-pass tile width: 0 = default for the length, or 8
+  bool col_seq = false;      // column pass: the two transforms of a thread one after the other
   int kb = 1;                // datasets per block of the fast adjoint density / closing passes
   int gsl = 0;               // g_c partial slices: ceil(K / kb) (fast), K (generic)
   int nhs = 0;               // spectrum row pitch: nx/2 (fast, folded) or nx/2 + 1
@@ -291,12 +292,18 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
     switch (p->g.ny) {
 #define X(N)                                                                                                   \
   case N:                                                                                                      \
-    if (p->col_tile == 8)                                                                                      \
-      PAT_LAUNCH((fast::k_col<N, MODE, 8>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st, \
-                         p->tb, SA, SB, scale, step, delta);                                                   \
-    else                                                                                                       \
-      PAT_LAUNCH((fast::k_col<N, MODE>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),                      \
-                         dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), 0, st, p->tb, SA, SB, scale, step, delta);  \
+    if (p->col_tile == 8 && p->col_seq)                                                                         \
+      PAT_LAUNCH((fast::k_col<N, MODE, 8, true>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st, \
+                 p->tb, SA, SB, scale, step, delta);                                                             \
+    else if (p->col_tile == 8)                                                                                  \
+      PAT_LAUNCH((fast::k_col<N, MODE, 8>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st,        \
+                 p->tb, SA, SB, scale, step, delta);                                                             \
+    else if (p->col_seq)                                                                                        \
+      PAT_LAUNCH((fast::k_col<N, MODE, fast::Cfg<N>::TC, true>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),     \
+                 dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), 0, st, p->tb, SA, SB, scale, step, delta);          \
+    else                                                                                                        \
+      PAT_LAUNCH((fast::k_col<N, MODE>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),                               \
+                 dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), 0, st, p->tb, SA, SB, scale, step, delta);          \
     return last_error();
       PAT_FAST_CASES(X)
 #undef X
@@ -942,6 +949,7 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   p->m = m;
   p->nh = nh;
   p->fast = fast_size(nx) && fast_size(ny) && !std::getenv("PAT_GENERIC_KERNELS");
+  p->col_seq = std::getenv("PAT_COL_SEQ") != nullptr;
   p->nhs = p->fast ? nx / 2 : nh;
   // 4 datasets per block: g_c traffic 2 B/pt instead of 8; 8 per block (one
   // block per CU at 107 KB of LDS) measured no faster at 512^2 x 8

@@ -178,60 +178,92 @@ class UNet:
         return self._flip[name]
 
     # -- forward / backward -----------------------------------------------------
-    def forward(self, x: torch.Tensor) -> torch.Tensor:
-        """``x [B][H][W][cin]`` bf16 -> ``r [B][H][W]`` float32 (a buffer of the net)."""
+    @staticmethod
+    def _run(probe, op: str, name: str, fn, ins: Dict, outs: Dict) -> None:
+        """Run one layer call; ``probe(stage, op, name, ins, outs)`` (if given)
+        sees its operands before ("pre") and after ("post") the call."""
+        if probe is not None:
+            probe("pre", op, name, ins, outs)
+        fn()
+        if probe is not None:
+            probe("post", op, name, ins, outs)
+
+    def forward(self, x: torch.Tensor, probe=None) -> torch.Tensor:
+        """``x [B][H][W][cin]`` bf16 -> ``r [B][H][W]`` float32 (a buffer of the net).
+        ``probe``: optional observer of every layer call (see ``_run``)."""
         B, H, W, C = x.shape
         if C != self.cin:
             raise ValueError(f"expected {self.cin} input channels")
         b = self.buffers(B, H, W)
         A = b["act"]
         self._x = x
+        run = self._run
         h = x
         for l in range(LEVELS):
             if l > 0:
-                nn.avgpool2(A[f"e{l - 1}b"], A[f"in{l}"])
+                xin, yout = A[f"e{l - 1}b"], A[f"in{l}"]
+                run(probe, "avgpool2", f"in{l}", lambda: nn.avgpool2(xin, yout), {"x": xin}, {"y": yout})
                 h = A[f"in{l}"]
-            nn.conv3x3(h, self.weight(f"e{l}a"), self.bias(f"e{l}a"), A[f"e{l}a"], relu=True)
-            nn.conv3x3(A[f"e{l}a"], self.weight(f"e{l}b"), self.bias(f"e{l}b"), A[f"e{l}b"], relu=True)
+            for name, xin in ((f"e{l}a", h), (f"e{l}b", A[f"e{l}a"])):
+                w, bias, y = self.weight(name), self.bias(name), A[name]
+                run(probe, "conv", name, lambda: nn.conv3x3(xin, w, bias, y, relu=True),
+                    {"x": xin, "w": w, "b": bias}, {"y": y})
         d = A[f"e{LEVELS - 1}b"]
         ch = b["ch"]
         for l in range(LEVELS - 2, -1, -1):
-            nn.upsample2(d, A[f"cat{l}"][..., ch[l]:])
-            nn.conv3x3(A[f"cat{l}"], self.weight(f"d{l}a"), self.bias(f"d{l}a"), A[f"d{l}a"], relu=True)
-            nn.conv3x3(A[f"d{l}a"], self.weight(f"d{l}b"), self.bias(f"d{l}b"), A[f"d{l}b"], relu=True)
+            up = A[f"cat{l}"][..., ch[l]:]
+            run(probe, "upsample2", f"cat{l}", lambda: nn.upsample2(d, up), {"x": d}, {"y": up})
+            for name, xin in ((f"d{l}a", A[f"cat{l}"]), (f"d{l}b", A[f"d{l}a"])):
+                w, bias, y = self.weight(name), self.bias(name), A[name]
+                run(probe, "conv", name, lambda: nn.conv3x3(xin, w, bias, y, relu=True),
+                    {"x": xin, "w": w, "b": bias}, {"y": y})
             d = A[f"d{l}b"]
-        nn.head(d, self.head_w(), self.head_b(), b["r"])
+        hw, hb, r = self.head_w(), self.head_b(), b["r"]
+        run(probe, "head", "head", lambda: nn.head(d, hw, hb, r), {"x": d, "w": hw, "b": hb}, {"r": r})
         self._key = (B, H, W)
         return b["r"]
 
-    def _layer_backward(self, b, name: str, x, dy, dx, mask) -> None:
+    def _layer_backward(self, b, name: str, x, dy, dx, mask, probe=None) -> None:
         """Weight / bias gradients of layer ``name`` (input x, pre-activation
         gradient dy) and, if dx is given, the data gradient (masked by the
         ReLU output that fed the layer, if any)."""
         gw, gb = self.grad_views(name)
-        nn.conv3x3_wgrad(x, dy, gw, gb, b["scratch"])
+        self._run(probe, "wgrad", name, lambda: nn.conv3x3_wgrad(x, dy, gw, gb, b["scratch"]),
+                  {"x": x, "dy": dy}, {"dw": gw, "db": gb})
         if dx is not None:
-            nn.conv3x3(dy, self.flipped(name), None, dx, mask=mask)
+            wt = self.flipped(name)
+            self._run(probe, "dgrad", name, lambda: nn.conv3x3(dy, wt, None, dx, mask=mask),
+                      {"dy": dy, "w": self.weight(name), "mask": mask}, {"dx": dx})
 
-    def backward(self, dr: torch.Tensor) -> None:
-        """Gradients of ``sum(dr * r)`` for the last forward into ``self.grad``."""
+    def backward(self, dr: torch.Tensor, probe=None) -> None:
+        """Gradients of ``sum(dr * r)`` for the last forward into ``self.grad``.
+        ``probe``: optional observer of every layer call (see ``_run``)."""
         b = self._bufs[self._key]
         A, G, ch = b["act"], b["grad"], b["ch"]
+        run = self._run
         hw = self.grad[self.head_off:self.head_off + self.base]
         hb = self.grad[self.head_off + self.base:self.head_off + self.base + 1]
-        nn.head_backward(A["d0b"], self.head_w(), dr.contiguous(), G["d0b"], hw, hb, b["scratch"])
+        drc = dr.contiguous()
+        run(probe, "head_backward", "head",
+            lambda: nn.head_backward(A["d0b"], self.head_w(), drc, G["d0b"], hw, hb, b["scratch"]),
+            {"x": A["d0b"], "w": self.head_w(), "dr": drc}, {"dx": G["d0b"], "dw": hw, "db": hb})
         for l in range(LEVELS - 1):
-            self._layer_backward(b, f"d{l}b", A[f"d{l}a"], G[f"d{l}b"], G[f"d{l}a"], A[f"d{l}a"])
-            self._layer_backward(b, f"d{l}a", A[f"cat{l}"], G[f"d{l}a"], G[f"cat{l}"], A[f"cat{l}"])
+            self._layer_backward(b, f"d{l}b", A[f"d{l}a"], G[f"d{l}b"], G[f"d{l}a"], A[f"d{l}a"], probe)
+            self._layer_backward(b, f"d{l}a", A[f"cat{l}"], G[f"d{l}a"], G[f"cat{l}"], A[f"cat{l}"], probe)
             below = f"d{l + 1}b" if l + 1 < LEVELS - 1 else f"e{LEVELS - 1}b"
-            nn.upsample2_backward(G[f"cat{l}"][..., ch[l]:], G[below], mask=A[below])
+            dyu, dxu, mu = G[f"cat{l}"][..., ch[l]:], G[below], A[below]
+            run(probe, "upsample2_backward", below, lambda: nn.upsample2_backward(dyu, dxu, mask=mu),
+                {"dy": dyu, "mask": mu}, {"dx": dxu})
         for l in range(LEVELS - 1, -1, -1):
-            self._layer_backward(b, f"e{l}b", A[f"e{l}a"], G[f"e{l}b"], G[f"e{l}a"], A[f"e{l}a"])
+            self._layer_backward(b, f"e{l}b", A[f"e{l}a"], G[f"e{l}b"], G[f"e{l}a"], A[f"e{l}a"], probe)
             if l > 0:
-                self._layer_backward(b, f"e{l}a", A[f"in{l}"], G[f"e{l}a"], G[f"in{l}"], None)
-                nn.avgpool2_backward(G[f"in{l}"], G[f"e{l - 1}b"], mask=A[f"e{l - 1}b"], accumulate=True)
+                self._layer_backward(b, f"e{l}a", A[f"in{l}"], G[f"e{l}a"], G[f"in{l}"], None, probe)
+                dyp, dxp, mp = G[f"in{l}"], G[f"e{l - 1}b"], A[f"e{l - 1}b"]
+                run(probe, "avgpool2_backward", f"e{l - 1}b",
+                    lambda: nn.avgpool2_backward(dyp, dxp, mask=mp, accumulate=True),
+                    {"dy": dyp, "mask": mp}, {"dx": dxp})
             else:
-                self._layer_backward(b, "e0a", self._x, G["e0a"], None, None)
+                self._layer_backward(b, "e0a", self._x, G["e0a"], None, None, probe)
 
     def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8) -> None:
         self.step += 1

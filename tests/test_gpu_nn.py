@@ -4,8 +4,8 @@ inputs.
 
 Tolerances follow from the arithmetic: products of bf16 operands are exact in
 float32, the float32 accumulation adds at most ~1e-5 of the sum of absolute
-terms S (computed by the oracle on |x|, |w|), and a bf16 result adds the
-rounding of 2^-9 relative (bound 2^-8 used).  Float32 outputs (weight
+terms S (computed by the oracle on |x|, |w|), and a bf16 result adds its
+rounding, at most the unit roundoff 2^-8 of bf16's 8-bit significand.  Float32 outputs (weight
 gradients, head) carry the accumulation term only.  Through the whole network
 the bf16 storage of every activation and gradient compounds, and a ReLU
 decision flips wherever the two sides' stored values straddle zero; so the
@@ -18,8 +18,13 @@ boundary moves by one unit, and such moves cascade through the layers
 (running the same oracle with float32 instead of float64 accumulation changes
 its 64 x 64, base-32 output by 7.0e-3 relative, the share of differing stored
 values growing from 2e-5 in the first layers to 29 % in the last).  The
-whole-network bars are therefore set at about three times that order
-sensitivity; the layer-level tests above carry the tight bounds.
+chained base-32 comparison therefore has a floor set by that sensitivity, not
+by the kernels: its bars are the BF16 bar 1e-2 for the output and the loss and
+5e-2 for the gradient, against the measured 7.3e-3 and 3.4e-2 of the
+64 x 64 case; the base-8 network, with few boundary crossings, keeps 1e-5.  The tight check
+of the network is tests/test_gpu_nn_replay.py: every layer call of a full-size
+forward and backward replayed on the GPU's own operands, within the per-layer
+bounds used here.
 """
 import numpy as np
 import pytest
@@ -344,9 +349,14 @@ def test_network_forward_and_gradient_match_oracle(shape):
     print(f"[nn] {shape}: vs bf16-storage oracle: output rel {e_r:.2e}, loss rel {e_L:.2e}, gradient rel "
           f"{e_all:.2e}, worst layer {worst} {errs[worst]:.2e}; bf16 storage vs full precision: output "
           f"{gap_r:.2e}, gradient {gap_g:.2e}, loss {abs(L_ref - L_full) / L_full:.2e}", flush=True)
-    assert e_r <= 2e-2 and e_L <= 1e-2
-    assert e_all <= 0.1
-    assert max(errs.values()) <= 0.2
+    if base == 8:
+        # few channels, few rounding-boundary crossings: the same roundings as the oracle
+        assert e_r <= 1e-5 and e_L <= 1e-5 and e_all <= 1e-5, (e_r, e_L, e_all)
+    else:
+        # the chained floor of the bf16-storage network (see the module docstring;
+        # every layer is checked at its own bound by tests/test_gpu_nn_replay.py)
+        assert e_r <= 1e-2 and e_L <= 1e-2, (e_r, e_L)
+        assert e_all <= 5e-2, e_all
     assert gap_r <= 2e-2 and gap_g <= 0.15
 
 
@@ -362,7 +372,7 @@ def test_network_forward_full_size_matches_oracle():
     r_ref, _ = U.unet_forward(p, x64, store=U.bf16_round)
     e = float(np.linalg.norm(r.cpu().numpy() - r_ref) / np.linalg.norm(r_ref))
     print(f"[nn] 512x512 forward rel {e:.2e} (bf16-storage oracle)", flush=True)
-    assert e <= 2e-2
+    assert e <= 1e-2
 
 
 def test_training_steps_reduce_the_loss():
