@@ -33,10 +33,13 @@ sys.path.insert(0, ROOT)
 from paper_2505_08482_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per grid point and launch of each fused pass (float32 state,
-# half spectra along x count 4 B/pt, c amortised over the K datasets).  The
-# adjoint density pass adds the g_c terms of ADJ_KB datasets per block, so the
-# g_c slice is read and written once per ADJ_KB datasets: 8 / ADJ_KB B/pt.
+# Bytes per grid point and launch of each fused pass (float32 state, half
+# spectra along x count 4 B/pt, c amortised over the K datasets).  Two counts
+# differ only in the adjoint density pass:
+# * algorithmic (what the method must move): the g_c accumulator is read and
+#   written once per time step for all K datasets, 8 / K B/pt;
+# * moved by this implementation: its blocks hold ADJ_KB datasets each, so the
+#   g_c slice is read and written once per ADJ_KB datasets, 8 / ADJ_KB B/pt.
 ADJ_KB = 4      # datasets per block of that pass at K >= 4
 
 
@@ -45,8 +48,11 @@ def progress(msg: str) -> None:
     print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
-def pass_bytes(K: int) -> dict:
+def pass_bytes(K: int, moved: bool = False) -> dict:
+    """Bytes per grid point of each pass: algorithmic, or (``moved``) what the
+    kernels move with their dataset grouping."""
     kb = ADJ_KB if K >= 4 else (2 if K >= 2 else 1)
+    gc_rw = 8.0 / kb if moved else 8.0 / K
     c_amort = 4.0 / K
     return {
         # r spectrum 4; w 2 spectra 8
@@ -59,8 +65,8 @@ def pass_bytes(K: int) -> dict:
         "fwd_row_rho": 32.0 + c_amort,
         # r 2 spectra 8; w 1 spectrum 4
         "adj_col_summ": 12.0,
-        # r spectrum 4 + rho^ 8 + history p 4 + c + g_c 8/kb; w rho^ 8 + g_c + 2 spectra 8
-        "adj_row_rho": 32.0 + c_amort + 8.0 / kb,
+        # r spectrum 4 + rho^ 8 + history p 4 + c + g_c; w rho^ 8 + g_c + 2 spectra 8
+        "adj_row_rho": 32.0 + c_amort + gc_rw,
         # r 2 spectra 8; w 2 spectra 8
         "adj_col_grad": 16.0,
         # r 2 spectra 8 + u^ 8; w u^ 8 + 2 spectra 8
@@ -103,19 +109,33 @@ def measured_traffic(kind: str, wl_name: str):
 
 
 def cpu_cores() -> int:
+    """Threads this process may run: its CPU affinity set, or the thread budget
+    the host gives it in OMP_NUM_THREADS if that is smaller (a shared host's
+    share of cores; os.cpu_count() counts cores that belong to other jobs)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
     env = os.environ.get("OMP_NUM_THREADS")
-    if env and env.isdigit():
+    if env and env.isdigit() and int(env) > 0:
         n = min(n, int(env))
-    return max(1, min(n, 16))
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(nt_sample: int, K: int, cores: int = 0) -> dict:
     """The float64 oracle, as it stands, on the W1 grid for nt_sample time samples
-    (on ``cores`` threads; 0 = all this process may use, at most 16)."""
+    (on ``cores`` threads; 0 = every thread this process may run)."""
     from oracle import kspace
     cores = cores or cpu_cores()
     kspace.WORKERS = cores
@@ -128,9 +148,19 @@ def cpu_baseline(nt_sample: int, K: int, cores: int = 0) -> dict:
     kspace.adjoint_gradient(wl.grid, wl.sensors, np.full_like(c, 1500.0), p0, resid, hist)
     dt = time.perf_counter() - t0
     pts = K * wl.grid.nx * wl.grid.ny * nt_sample
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    # the oracle's cost is linear in the number of time samples: the full
+    # 4000-sample evaluation is this sample's time scaled by 4000 / nt_sample
     return {"value": pts / dt, "unit": "grid-pt-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"float64 oracle (numpy + scipy.fft, {cores} threads), forward + adjoint on the "
-                      f"512x512 grid, K={K}, {nt_sample} time samples ({dt:.1f} s)"}
+                      f"512x512 grid, K={K}, {nt_sample} time samples ({dt:.1f} s)",
+            "extrapolated_eval_seconds_nt4000": round(dt * 4000.0 / nt_sample, 1),
+            "extrapolation": f"linear in the number of time samples, {nt_sample} -> 4000 (extrapolated)",
+            "host": {"cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity,
+                     "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}}
 
 
 def forward_only(plan, wl, c, p0, data, ws, reps=2):
@@ -263,7 +293,7 @@ def batch_w3(evals: int):
         wl = I.config2(n=n, K=K, nt=nt)
         c_true, p0 = I.phantoms(wl, 4, case=i)
         plan = pat.Plan(wl.grid, K, wl.sensors)
-        plan.set_tile(tune.tile_for(n, K))
+        tune.apply(plan, n, K)
         T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
         j = {"plan": plan, "c": T(np.full_like(c_true, 1500.0)), "p0": T(p0), "ws": plan.workspace(0),
              "data": torch.empty(plan.data_shape, device="cuda"), "w": T(np.full(K, 100.0))}
@@ -290,19 +320,25 @@ def batch_w3(evals: int):
         sequential()
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t
+    ref = [(j["g_c"].clone(), j["g_p0"].clone(), j["J"].clone()) for j in jobs]
     ns = tune.streams_for(jobs, label="w3_seed4000")
     t = time.perf_counter()
     for _ in range(evals):
         pat.batch_gradient(jobs, ns)
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t
+    same = all(torch.equal(j["g_c"], r[0]) and torch.equal(j["g_p0"], r[1]) and torch.equal(j["J"], r[2])
+               for j, r in zip(jobs, ref))
+    classes = sorted({j["plan"].grid.nx for j in jobs})
     for j in jobs:
         j["plan"].close()
-    return {"problems": 32, "evals_each": evals, "streams": ns,
-            "tiles": sorted({(j["plan"].grid.nx, j["plan"].K) for j in jobs}).__len__(),
+    return {"problems": 32, "evals_each": evals, "streams": ns, "classes": classes,
             "batched_value": pts / t_bat, "sequential_value": pts / t_seq, "unit": "grid-pt-steps/s",
             "speedup": round(t_seq / t_bat, 3), "seconds_batched": round(t_bat, 3),
-            "seconds_sequential": round(t_seq, 3)}
+            "seconds_sequential": round(t_seq, 3), "batched_equals_sequential_bitwise": bool(same),
+            "schedule": "problems of one grid size share every launch (one launch per pass), forward solves "
+                        "aligned at their ends and adjoint solves at their starts, captured step-chunk graphs "
+                        "per active set, one stream per grid size"}
 
 
 def time_to_solution(wl_fine, c_true, y_fine, w, iters: int, target: float = 2.0):
@@ -429,10 +465,12 @@ def main() -> int:
     plan = pat.Plan(g, wl.K, wl.sensors)
     if args.tile == "auto":
         from paper_2505_08482_amd import tune
-        tile = tune.tile_for(g.nx, wl.K)     # measured once per GPU type and cached
+        cfg = tune.launch_for(g.nx, wl.K)    # the committed table for this GPU type, else measured
+        tile, col_seq = cfg["tile"], cfg["seq"]
     else:
-        tile = int(args.tile)
+        tile, col_seq = int(args.tile), 0
     plan.set_tile(tile)
+    plan.set_col_order(col_seq)
     t_c_true = torch.from_numpy(c_true.astype(np.float32)).to(dev)
     t_p0 = torch.from_numpy(p0.astype(np.float32)).to(dev)
     ws = plan.workspace(args.ckpt)
@@ -478,6 +516,7 @@ def main() -> int:
 
     tr = pat.trace_read()
     PB = pass_bytes(wl.K)
+    PBM = pass_bytes(wl.K, moved=True)
     # measured bytes of the dominant pass (set below once it is known)
     tb = None
     shares = {k: v[1] / max(v[0], 1) for k, v in tr.items()}   # average launch duration, ms
@@ -506,7 +545,7 @@ def main() -> int:
         "config": {"workload": wl.name, "grid": f"{g.nx}x{g.ny}", "K": wl.K, "nt": g.nt, "sensors": wl.m,
                    "dx_m": g.dx, "dt_s": g.dt, "pml": g.pml,
                    "history": "store-all" if args.ckpt == 0 else f"checkpoint every {args.ckpt}",
-                   "column_tile": tile or "default",
+                   "column_tile": tile or "default", "column_order": "sequential" if col_seq else "together",
                    "step": "recorded forward + misfit + adjoint gradient (g_p0 for all K, g_c)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -514,10 +553,17 @@ def main() -> int:
                      "traffic_bytes_per_launch": tb, "algorithmic_bytes_per_launch": PB[dom] * units,
                      "kernel": dom,
                      "avg_us": round(1000.0 * avg_ms, 2), "bytes_per_point": PB[dom],
+                     "bytes_per_point_moved": PBM[dom],
                      "units_per_launch": units,
                      "timing": "HIP start/stop events attached to the kernel dispatch (hipExtLaunchKernelGGL) "
                                "on the launch stream, every %d-th launch of each pass, in one evaluation launched "
-                               "kernel by kernel right after the timed (graph-replayed) ones" % args.trace_every},
+                               "kernel by kernel right after the timed (graph-replayed) ones" % args.trace_every,
+                     # the whole time step (all eight passes, the figure the 50 % target is about):
+                     # algorithmic bytes per grid-point step x grid-point steps per second
+                     "step": {"bytes_per_point_step": sum(PB.values()),
+                              "achieved": round(sum(PB.values()) * value / 1e9, 1),
+                              "frac": round(sum(PB.values()) * value / 1e9 / HBM_PEAK_GBS, 4),
+                              "rate_at_half_peak": round(0.5 * HBM_PEAK_GBS * 1e9 / sum(PB.values()), 1)}},
         "step_alg_GBps": round(sum(PB.values()) * pts / (ms / 1000.0) / 1e9, 1),
         "passes": passes,
         "J": float(J.item()),
@@ -538,6 +584,8 @@ def main() -> int:
             except Exception as e:   # an extra must never cost the main line
                 out[name] = {"error": f"{type(e).__name__}: {e}"}
             progress(f"{name} done")
+        if isinstance(out.get("batch"), dict) and "batched_value" in out["batch"]:
+            out["batch"]["batched_over_w1_rate"] = round(out["batch"]["batched_value"] / value, 3)
     if not args.no_cpu:
         progress("cpu_baseline ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, wl.K)

@@ -26,7 +26,11 @@
  *    instead of replaying captured step graphs (same bits);
  *    PAT_GENERIC_KERNELS (any value, read by pat_plan_create) selects the
  *    any-radix LDS kernels also for power-of-two grids (same results to
- *    float32 rounding).
+ *    float32 rounding); PAT_CHECK_FINITE (any value, read by pat_plan_create)
+ *    turns on the check mode of the plan: pat_forward and
+ *    pat_adjoint_gradient then scan their outputs, synchronize the stream and
+ *    return PAT_ENONFINITE if any value is NaN or infinite (a debugging aid:
+ *    the synchronisation makes these calls unusable under graph capture).
  */
 #ifndef PAT_H
 #define PAT_H
@@ -43,6 +47,7 @@ extern "C" {
 #define PAT_EUNSUPPORTED -2  /* grid length without a compiled FFT plan, K > 64   */
 #define PAT_EWORKSPACE   -3  /* workspace too small, or not filled by pat_forward */
 #define PAT_EHIP         -4  /* HIP runtime error (launch or allocation)          */
+#define PAT_ENONFINITE   -5  /* an output holds NaN or Inf (check mode only)       */
 
 /* One computational grid.  nx, ny include the PML.  The time axis holds nt
  * samples t_n = n*dt, n = 0..nt-1 (nt-1 updates).  c_ref is the fixed speed of
@@ -128,9 +133,9 @@ int pat_project_update(int64_t n, float* x, const float* d, float alpha,
 /* Sec. 3.1: bilinear interpolation of nchan coarse fields [nchan][nyc][nxc]
  * onto a finer grid [nchan][nyf][nxf] covering the same physical square
  * (cell-centred pixels), clamped at the border.  Each fine value is a convex
- * combination of at most four coarse values. */
-int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc,
-                float* fine, int32_t nyf, int32_t nxf, void* stream);
+ * combination of at most four coarse values.  Sizes are given x first. */
+int pat_prolong(int32_t nchan, const float* coarse, int32_t nxc, int32_t nyc,
+                float* fine, int32_t nxf, int32_t nyf, void* stream);
 
 /* Sec. 3.1 for levels of different physical extent (Table 1's grids carry PML
  * layers of different widths): bilinear interpolation of nchan coarse fields
@@ -139,8 +144,8 @@ int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc,
  * (i + 1/2 - n/2) * dx), each fine value taken at its own physical position
  * and clamped to the coarse grid.  Equals pat_prolong when nxc * dxc ==
  * nxf * dxf.  PAT_EINVAL for null arrays, non-positive sizes or spacings. */
-int pat_prolong_phys(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, double dxc,
-                     float* fine, int32_t nyf, int32_t nxf, double dxf, void* stream);
+int pat_prolong_phys(int32_t nchan, const float* coarse, int32_t nxc, int32_t nyc, double dxc,
+                     float* fine, int32_t nxf, int32_t nyf, double dxf, void* stream);
 
 /* Sec. 4.1.2: linear interpolation in time of traces y [nlead][nt_src][m]
  * sampled at n*dt_src onto out [nlead][nt_dst][m] at n*dt_dst (held at the
@@ -183,6 +188,15 @@ int pat_dot(int64_t n, const float* a, const float* b, double* out, void* scratc
  * when it changes.  PAT_EINVAL for other values. */
 int pat_plan_set_tile(pat_plan* plan, int32_t col_tile);
 
+/* Column-pass transform order of a plan (power-of-two grids): 0 = the two
+ * transforms a thread holds advance stage by stage together (shared
+ * barriers; the default), 1 = one after the other (the first array's loads
+ * issued first, so its transform starts while the second array's loads land,
+ * and its result is stored while the second is transformed).  A tuning knob
+ * (results are identical); captured step graphs of the plan are discarded
+ * when it changes.  PAT_EINVAL for other values. */
+int pat_plan_set_col_order(pat_plan* plan, int32_t sequential);
+
 /* One independent problem of a batch: everything a forward + misfit +
  * adjoint evaluation needs (as for pat_forward / pat_misfit /
  * pat_adjoint_gradient with store-all history, ckpt_every = 0). */
@@ -200,6 +214,12 @@ typedef struct pat_problem {
   void* ws;            /* workspace of pat_workspace_size(plan, 0) bytes */
   size_t ws_bytes;
 } pat_problem;
+
+/* Destroy the library's internal batch streams (created by the first
+ * pat_batch_gradient and kept for later batches) once the work queued on them
+ * has finished.  The next batch creates them again.  Not to be called while
+ * a batch is being enqueued from another thread. */
+int pat_batch_release(void);
 
 /* Objective and gradient (eqs. (4)-(9)) of `nprob` independent problems of
  * any sizes at once: the problems are spread over `nstreams` (1..16) internal

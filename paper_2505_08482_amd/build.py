@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpat.so")
 ARCH = "gfx950"
-SOURCES = ("pat_api.hip", "nn_api.hip")
+SOURCES = ("pat_api.hip", "batch_launch.hip", "nn_api.hip")
 
 
 def hipcc() -> str:

@@ -226,7 +226,7 @@ template <int N> struct RowF {
   using RC = RowF<N>;                                                          \
   constexpr int T = RC::T;                                                     \
   const int K = tb.K, ny = tb.ny, nhf = N / 2;                                 \
-  const int k = blockIdx.x % K, ybase = (blockIdx.x / K) * RC::ROWS;           \
+  const int k = bid % K, ybase = (bid / K) * RC::ROWS;                         \
   const int tid = threadIdx.x, q = tid % T;                                    \
   const int grp = RC::G == 1 ? 0 : tid / T, lane_base = grp * T; /* uniform at G = 1 */ \
   const int y0 = ybase + 2 * grp, y1 = y0 + 1;                                 \
@@ -236,10 +236,10 @@ template <int N> struct RowF {
 
 // n = 0: rho = p0/(2c^2), history, sensors, spectra of p0 (rows y0, y1 share one FFT)
 template <int N>
-__global__ __launch_bounds__(64) void k_fwd_init(Tables tb, const float* __restrict__ c, const float* __restrict__ p0,
-                                                 float* __restrict__ rx, float* __restrict__ ry,
-                                                 float* __restrict__ hist0, float* __restrict__ dpart,
-                                                 float2* __restrict__ SA) {
+__device__ __forceinline__ void k_fwd_init_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                                const float* __restrict__ p0, float* __restrict__ rx,
+                                                float* __restrict__ ry, float* __restrict__ hist0,
+                                                float* __restrict__ dpart, float2* __restrict__ SA) {
   PAT_ROW_PROLOGUE(N)
   __shared__ float2 X[RC::G][Lds<N>::P];
   __shared__ float P[RC::ROWS][N];
@@ -275,11 +275,19 @@ __global__ __launch_bounds__(64) void k_fwd_init(Tables tb, const float* __restr
   if (y1 < ny) unpack_store<N>(v[0], q, lane_base, ra, rb);
 }
 
+template <int N>
+__global__ __launch_bounds__(64) void k_fwd_init(Tables tb, const float* __restrict__ c, const float* __restrict__ p0,
+                                                 float* __restrict__ rx, float* __restrict__ ry,
+                                                 float* __restrict__ hist0, float* __restrict__ dpart,
+                                                 float2* __restrict__ SA) {
+  fast::k_fwd_init_body<N>(blockIdx.x, tb, c, p0, rx, ry, hist0, dpart, SA);
+}
+
 // velocity update (step 0: u^{-1/2} = G/2), spectra of (u_x + i u_y)
 template <int N>
-__global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux, float* __restrict__ uy,
-                                              float2* __restrict__ SA, float2* __restrict__ SB,
-                                              const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_fwd_u_body(const int bid, const Tables& tb, float* __restrict__ ux,
+                                             float* __restrict__ uy, float2* __restrict__ SA, float2* __restrict__ SB,
+                                             const StepCtl* __restrict__ ctl) {
   PAT_ROW_PROLOGUE(N)
   const int first = ctl->fwd_n == 0;
   __shared__ float2 X[RC::G][2][Lds<N>::P];
@@ -351,12 +359,20 @@ __global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux,
   }
 }
 
+template <int N>
+__global__ __launch_bounds__(64) void k_fwd_u(Tables tb, float* __restrict__ ux, float* __restrict__ uy,
+                                              float2* __restrict__ SA, float2* __restrict__ SB,
+                                              const StepCtl* __restrict__ ctl) {
+  fast::k_fwd_u_body<N>(blockIdx.x, tb, ux, uy, SA, SB, ctl);
+}
+
 // density / pressure update, history, sensors at n+1, spectra of p (rows y0, y1 share one FFT)
 template <int N>
-__global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restrict__ c, float* __restrict__ rx,
-                                                float* __restrict__ ry, float* __restrict__ hist_base,
-                                                float* __restrict__ dpart, float2* __restrict__ SA,
-                                                const float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                               float* __restrict__ rx, float* __restrict__ ry,
+                                               float* __restrict__ hist_base, float* __restrict__ dpart,
+                                               float2* __restrict__ SA, const float2* __restrict__ SB,
+                                               const StepCtl* __restrict__ ctl) {
   PAT_ROW_PROLOGUE(N)
   const int n = ctl->fwd_n;
   float* hist = hist_base ? hist_base + (size_t)(n + 1 - ctl->hist_first) * tb.K * ny * N : nullptr;
@@ -460,6 +476,14 @@ __global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restri
   }
 }
 
+template <int N>
+__global__ __launch_bounds__(64) void k_fwd_rho(Tables tb, const float* __restrict__ c, float* __restrict__ rx,
+                                                float* __restrict__ ry, float* __restrict__ hist_base,
+                                                float* __restrict__ dpart, float2* __restrict__ SA,
+                                                const float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
+  fast::k_fwd_rho_body<N>(blockIdx.x, tb, c, rx, ry, hist_base, dpart, SA, SB, ctl);
+}
+
 // Adjoint row passes that touch g_c run KB datasets per block (one wave per
 // dataset, same rows): each wave leaves its per-pixel g_c term in LDS and the
 // block adds the KB terms in dataset order to one g_c slice per dataset group,
@@ -473,10 +497,10 @@ struct AdjBlk {
   static constexpr int NR = RC::ROWS * N / (64 * KB);   // reduced pixels per thread
   int G, kg, ybase, wave, lane, kw, k, grp, q, lane_base, y0, y1;
   bool act, ok;
-  __device__ __forceinline__ AdjBlk(const Tables& tb) {
+  __device__ __forceinline__ AdjBlk(const Tables& tb, int bid) {
     G = (tb.K + KB - 1) / KB;
-    kg = blockIdx.x % G;
-    ybase = (blockIdx.x / G) * RC::ROWS;
+    kg = bid % G;
+    ybase = (bid / G) * RC::ROWS;
     wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);   // wave-uniform: scalar row addresses
     lane = threadIdx.x % 64;
     kw = kg * KB + wave;
@@ -517,15 +541,14 @@ struct AdjBlk {
 // (a_x rh_x + i a_y rh_y); rh <- a^2 rh.  Every global load (spectra, state,
 // history, g_c slice, sensor injections) is issued before the first transform.
 template <int N, int KB>
-__global__ __launch_bounds__(64 * KB) void k_adj_rho(Tables tb, const float* __restrict__ c,
-                                                     const float* __restrict__ hist_base,
-                                                     const float* __restrict__ resid, float* __restrict__ rhx,
-                                                     float* __restrict__ rhy, float* __restrict__ gcg,
-                                                     float2* __restrict__ SA, float2* __restrict__ SB,
-                                                     const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                               const float* __restrict__ hist_base, const float* __restrict__ resid,
+                                               float* __restrict__ rhx, float* __restrict__ rhy,
+                                               float* __restrict__ gcg, float2* __restrict__ SA,
+                                               float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   using RC = RowF<N>;
   constexpr int T = RC::T;
-  const AdjBlk<N, KB> b(tb);
+  const AdjBlk<N, KB> b(tb, bid);
   const int ny = tb.ny, nhf = N / 2, k = b.k, grp = b.grp, q = b.q, y0 = b.y0;
   const bool ok = b.ok, st = b.ok && b.act;
   Fft<N> fft;
@@ -657,12 +680,22 @@ __global__ __launch_bounds__(64 * KB) void k_adj_rho(Tables tb, const float* __r
   }
 }
 
+template <int N, int KB>
+__global__ __launch_bounds__(64 * KB) void k_adj_rho(Tables tb, const float* __restrict__ c,
+                                                     const float* __restrict__ hist_base,
+                                                     const float* __restrict__ resid, float* __restrict__ rhx,
+                                                     float* __restrict__ rhy, float* __restrict__ gcg,
+                                                     float2* __restrict__ SA, float2* __restrict__ SB,
+                                                     const StepCtl* __restrict__ ctl) {
+  fast::k_adj_rho_body<N, KB>(blockIdx.x, tb, c, hist_base, resid, rhx, rhy, gcg, SA, SB, ctl);
+}
+
 // adjoint velocities: uh <- as^2 uh + (inverse rows of PAIRP spectra);
 // spectra of (w_x uh_x + i w_y uh_y), w = as, or as - as^2/2 at adjoint step n = 1
 template <int N>
-__global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx, float* __restrict__ uhy,
-                                              float2* __restrict__ SA, float2* __restrict__ SB,
-                                              const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_adj_u_body(const int bid, const Tables& tb, float* __restrict__ uhx,
+                                             float* __restrict__ uhy, float2* __restrict__ SA,
+                                             float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   PAT_ROW_PROLOGUE(N)
   const int final_ = ctl->adj_n == 1;
   __shared__ float2 X[RC::G][2][Lds<N>::P];
@@ -730,17 +763,24 @@ __global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx
   }
 }
 
+template <int N>
+__global__ __launch_bounds__(64) void k_adj_u(Tables tb, float* __restrict__ uhx, float* __restrict__ uhy,
+                                              float2* __restrict__ SA, float2* __restrict__ SB,
+                                              const StepCtl* __restrict__ ctl) {
+  fast::k_adj_u_body<N>(blockIdx.x, tb, uhx, uhy, SA, SB, ctl);
+}
+
 // closing terms of the adjoint: g_p0 and the initial-state part of g_c
 // (summed over the block's datasets into the group's g_c slice)
 template <int N, int KB>
-__global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* __restrict__ c,
-                                                       const float* __restrict__ p0, const float* __restrict__ resid0,
-                                                       const float* __restrict__ rhx, const float* __restrict__ rhy,
-                                                       float* __restrict__ gcg, float* __restrict__ gp0,
-                                                       const float2* __restrict__ SA) {
+__device__ __forceinline__ void k_adj_final_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                                 const float* __restrict__ p0, const float* __restrict__ resid0,
+                                                 const float* __restrict__ rhx, const float* __restrict__ rhy,
+                                                 float* __restrict__ gcg, float* __restrict__ gp0,
+                                                 const float2* __restrict__ SA) {
   using RC = RowF<N>;
   constexpr int T = RC::T;
-  const AdjBlk<N, KB> b(tb);
+  const AdjBlk<N, KB> b(tb, bid);
   const int ny = tb.ny, nhf = N / 2, k = b.k, grp = b.grp, q = b.q, y0 = b.y0;
   const bool ok = b.ok;
   Fft<N> fft;
@@ -783,6 +823,15 @@ __global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* _
   b.reduce_store(tb, PH, gp, gcg);
 }
 
+template <int N, int KB>
+__global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* __restrict__ c,
+                                                       const float* __restrict__ p0, const float* __restrict__ resid0,
+                                                       const float* __restrict__ rhx, const float* __restrict__ rhy,
+                                                       float* __restrict__ gcg, float* __restrict__ gp0,
+                                                       const float2* __restrict__ SA) {
+  fast::k_adj_final_body<N, KB>(blockIdx.x, tb, c, p0, resid0, rhx, rhy, gcg, gp0, SA);
+}
+
 // ===========================================================================
 // Column pass (transform length NY = N), nx/2 folded columns, TC per block
 // ===========================================================================
@@ -792,9 +841,9 @@ __global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* _
 // loads land, and the first output is stored while the second is transformed)
 // instead of stage by stage together (shared barriers).  Same arithmetic.
 template <int N, int MODE, int TC = Cfg<N>::TC, bool SEQ = false>
-__global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
-                                                                float2* __restrict__ SB, float scale,
-                                                                int32_t* __restrict__ step, int32_t delta) {
+__device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, float2* __restrict__ SA,
+                                           float2* __restrict__ SB, float scale, int32_t* __restrict__ step,
+                                           int32_t delta) {
   constexpr int T = Cfg<N>::T, P = LdsCol<N, TC>::P;
   static_assert((TC == 4 && P % 16 == 4) || (TC == 8 && P % 16 == 2) || (TC >= 16 && P % 2 == 1),
                 "column pitch");
@@ -803,7 +852,7 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
   __shared__ float2 LA[TC * P];
   __shared__ float2 LB[(TWO_IN || TWO_OUT) ? TC * P : 1];
   const int K = tb.K, nx = tb.nx, nhf = nx / 2, nh = tb.nh;
-  const int k = blockIdx.x % K, c0 = (blockIdx.x / K) * TC;
+  const int k = bid % K, c0 = (bid / K) * TC;
   const int tid = threadIdx.x, cl = tid % TC, q = tid / TC, cx = c0 + cl;
   const bool ok = cx < nhf;
   // dataset base pointers (block-uniform) + 32-bit byte offsets per lane and row
@@ -944,7 +993,14 @@ __global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __res
   // first pass of a step: advance the step counter (read by the row passes
   // that follow, not by this one), after the stores so that no block waits
   // for it before its own loads
-  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;
+  if (step && bid == 0 && threadIdx.x == 0) *step += delta;
+}
+
+template <int N, int MODE, int TC = Cfg<N>::TC, bool SEQ = false>
+__global__ __launch_bounds__(TC * Cfg<N>::T) void k_col(Tables tb, float2* __restrict__ SA,
+                                                                float2* __restrict__ SB, float scale,
+                                                                int32_t* __restrict__ step, int32_t delta) {
+  fast::k_col_body<N, MODE, TC, SEQ>(blockIdx.x, tb, SA, SB, scale, step, delta);
 }
 
 }  // namespace fast

@@ -8,7 +8,9 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
+#include <utility>
 #include <new>
 #include <vector>
 
@@ -17,6 +19,7 @@
 #include "wave_kernels.hpp"
 #include "fast_kernels.hpp"
 #include "prior_kernels.hpp"
+#include "batch_slot.hpp"
 
 using namespace pat;
 
@@ -97,6 +100,8 @@ struct pat_plan {
   bool fast = false;         // register-resident power-of-two passes (folded spectra)
   int col_tile = 0;          // column-pass tile width: 0 = default for the length, or 8
   bool col_seq = false;      // column pass: the two transforms of a thread one after the other
+  bool check_finite = false; // check mode: scan outputs, return PAT_ENONFINITE on NaN / Inf
+  int32_t* flag = nullptr;   // device flag of the check mode
   int kb = 1;                // datasets per block of the fast adjoint density / closing passes
   int gsl = 0;               // g_c partial slices: ceil(K / kb) (fast), K (generic)
   int nhs = 0;               // spectrum row pitch: nx/2 (fast, folded) or nx/2 + 1
@@ -445,6 +450,23 @@ int set_ctl(hipStream_t st, StepCtl* ctl, int mask, int fwd_n, int adj_n, int hi
     if (_s != PAT_OK) return _s; \
   } while (0)
 
+// Check mode: PAT_ENONFINITE if any of the arrays holds a NaN or an infinity
+// (clears the plan's flag with a kernel, scans, copies the flag back and
+// synchronizes the stream).
+int check_outputs(const pat_plan* p, hipStream_t st, std::initializer_list<std::pair<const float*, int64_t>> arrays) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, p->flag, 0);
+  PAT_TRY(last_error());
+  for (const auto& a : arrays) {
+    hipLaunchKernelGGL(k_flag_nonfinite, dim3(grid_blocks(a.second)), dim3(256), 0, st, a.first, a.second, p->flag);
+    PAT_TRY(last_error());
+  }
+  int32_t h = 0;
+  if (hipMemcpyAsync(&h, p->flag, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return PAT_EHIP;
+  return h ? PAT_ENONFINITE : PAT_OK;
+}
+
 // Arguments of a run of time steps (identical for every step of the run).
 struct FwdArgs {
   const float* c;
@@ -604,9 +626,18 @@ void pml_axis(const pat_grid& g, int n, std::vector<float>& a, std::vector<float
 namespace {
 
 // ----------------------------------------------------------------------------
-// Batch execution of independent problems on a pool of internal streams
+// Batch executor.  Problems of one transform family and grid size form a
+// class; the time steps of a class's problems advance in shared launches
+// (batch_kernels.hpp), one stream per class.  The forward solves are aligned
+// at their ends (a problem with fewer steps starts later) and the adjoint
+// solves at their starts, so that between two start (or end) points the set
+// of active problems is fixed: an epoch.  Each epoch has its slot tables in
+// device memory, and its runs of up to kChunk steps are captured as graphs
+// once and replayed.  Per-problem work (initial state, misfit, closing terms)
+// is launched per problem.  A context (slot tables, graphs) is kept for the
+// last batch and reused while the same problems come back.
 // ----------------------------------------------------------------------------
-std::vector<hipStream_t> g_pool;   // created on first use, never destroyed (process lifetime)
+std::vector<hipStream_t> g_pool;   // created on first use, destroyed by pat_batch_release
 
 int pool_streams(int n) {
   while ((int)g_pool.size() < n) {
@@ -617,81 +648,418 @@ int pool_streams(int n) {
   return PAT_OK;
 }
 
-// One problem's objective + gradient as a sequence of enqueueable units.
-struct BatchJob {
+struct BatchProb {
   pat_problem pr;
   Layout L;
   FwdArgs f;
   AdjArgs a;
-  int phase = 0;     // 0 fwd prologue, 1 fwd steps, 2 misfit + adj prologue, 3 adj steps, 4 closing, 5 done
-  int next = 0;      // next step index of the current phase
-  double cost = 0;   // K * nx * ny * nt (for the schedule)
+  int steps = 0;      // nt - 1 updates in each direction
+  int col = 0, row = 0, adj = 0;   // blocks of one launch of each kind
+};
+
+struct SlotRange {     // a slot table in the context's device blob
+  size_t off = 0;      // in slots
+  int n = 0;
+  int blocks = 0;      // total blocks of the launch over these slots
+  int kb = 1;          // datasets per block (adjoint density, power-of-two family)
+};
+
+struct BatchEpoch {
+  int begin = 0, end = 0;        // global steps [begin, end)
+  SlotRange col, row;
+  std::vector<SlotRange> adj;    // per group of equal datasets per block
+  std::vector<int> starting;     // forward: members whose solve starts at `begin`
+  std::vector<int> ending;       // adjoint: members whose solve ends at `end`
+};
+
+struct BatchClass {
+  int nx = 0, ny = 0;
+  bool fast = false;
+  std::vector<int> members;
+  int T = 0;
+  std::vector<BatchEpoch> fwd, adj;
+  std::vector<int> no_steps;     // members with nt = 1
   int stream = 0;
 };
 
-int job_unit(BatchJob& j, hipStream_t st) {
-  pat_plan* p = j.pr.plan;
-  const pat_grid& g = p->g;
-  auto fbody = [](pat_plan* pp, hipStream_t s2, const FwdArgs& aa, int cnt) { return fwd_steps(pp, s2, aa, cnt); };
-  auto abody = [](pat_plan* pp, hipStream_t s2, const AdjArgs& aa, int cnt) { return adj_steps(pp, s2, aa, cnt); };
-  switch (j.phase) {
-    case 0:
-      PAT_TRY(set_ctl(st, j.f.ctl, 1 | 4, -1, 0, 0));
-      PAT_TRY(launch_fwd_init(p, st, j.pr.c, j.pr.p0, j.f.rx, j.f.ry, j.f.hist_base, j.f.dpart, j.f.SA));
-      j.phase = 1;
-      j.next = 0;
-      return PAT_OK;
-    case 1: {
-      const int steps = g.nt - 1;
-      const int cnt = std::min(kChunk, steps - j.next);
-      if (cnt > 0) PAT_TRY(run_steps(p, st, j.f, cnt, 1, fbody));
-      j.next += std::max(cnt, 0);
-      if (j.next >= steps) j.phase = 2;
-      return PAT_OK;
-    }
-    case 2: {
-      const int64_t rows = (int64_t)p->K * g.nt;
-      hipLaunchKernelGGL(k_sensor_finalize, dim3(grid_blocks(rows * p->m)), dim3(256), 0, st, j.f.dpart, j.pr.data,
-                         rows, p->m);
-      PAT_TRY(last_error());
-      const int64_t per_k = (int64_t)g.nt * p->m;
-      hipLaunchKernelGGL(k_misfit, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, j.pr.data, j.pr.y, j.pr.w, j.pr.resid,
-                         p->red, per_k, p->K);
-      PAT_TRY(last_error());
-      hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, st, p->red, RED_BLOCKS, j.pr.J, 0.5);
-      PAT_TRY(last_error());
-      PAT_TRY(fill_zero(st, j.a.uhx, j.L.F));
-      PAT_TRY(fill_zero(st, j.a.uhy, j.L.F));
-      PAT_TRY(fill_zero(st, j.a.rhx, j.L.F));
-      PAT_TRY(fill_zero(st, j.a.rhy, j.L.F));
-      PAT_TRY(fill_zero(st, j.a.gck, j.L.F));
-      PAT_TRY(fill_zero(st, j.a.SC, j.L.Sp));
-      PAT_TRY(fill_zero(st, j.a.SD, j.L.Sp));
-      PAT_TRY(set_ctl(st, j.a.ctl, 2 | 4, 0, g.nt, 0));
-      j.phase = 3;
-      j.next = g.nt - 1;
-      return PAT_OK;
-    }
-    case 3: {
-      const int cnt = std::min(kChunk, j.next);
-      if (cnt > 0) PAT_TRY(run_steps(p, st, j.a, cnt, 2, abody));
-      j.next -= std::max(cnt, 0);
-      if (j.next < 1) j.phase = 4;
-      return PAT_OK;
-    }
-    case 4: {
-      const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
-      PAT_TRY(launch_col<COL_SUMM>(p, st, j.a.SC, j.a.SD, (float)(g.dt / g.rho0 * nrm), nullptr, 0));
-      PAT_TRY(launch_adj_final(p, st, j.pr.c, j.pr.p0, j.pr.resid, j.a.rhx, j.a.rhy, j.a.gck, j.pr.g_p0, j.a.SC));
-      const int64_t npix = (int64_t)g.ny * g.nx;
-      hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, j.a.gck, j.pr.g_c, p->gsl, npix);
-      PAT_TRY(last_error());
-      j.phase = 5;
-      return PAT_OK;
-    }
-    default:
-      return PAT_OK;
+struct BatchGraph {
+  uint64_t key;
+  hipGraphExec_t exec;
+  hipEvent_t done;
+};
+
+struct BatchContext {
+  uint64_t sig = 0;
+  std::vector<BatchProb> probs;
+  std::vector<BatchClass> classes;
+  std::vector<BatchSlot> host;   // every slot table
+  BatchSlot* dev = nullptr;
+  std::vector<BatchGraph> graphs;
+  hipStream_t cap = nullptr;
+};
+
+BatchContext* g_batch = nullptr;
+
+void batch_free(BatchContext* c) {
+  if (!c) return;
+  for (auto& g : c->graphs) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
+    (void)hipGraphExecDestroy(g.exec);
   }
+  if (c->dev) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->dev);
+  }
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
+
+uint64_t fnv(uint64_t h, const void* data, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+// Blocks of one launch of each kind for a problem (the single-problem launch shapes).
+int launch_blocks(const pat_plan* p, int* col, int* row, int* adj) {
+  if (p->fast) {
+    switch (p->g.nx) {
+#define X(N)                                                  \
+  case N:                                                     \
+    *row = frows_blocks<N>(p);                                \
+    *adj = fadj_blocks<N>(p);                                 \
+    break;
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+    switch (p->g.ny) {
+#define X(N)                                                  \
+  case N:                                                     \
+    *col = fcols_blocks(p, fast::Cfg<N>::TC);                 \
+    break;
+      PAT_FAST_CASES(X)
+#undef X
+      default: return PAT_EUNSUPPORTED;
+    }
+    return PAT_OK;
+  }
+  switch (p->g.nx) {
+#define X(N)                                                  \
+  case N:                                                     \
+    *row = rows_blocks<N>(p);                                 \
+    *adj = *row;                                              \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  switch (p->g.ny) {
+#define X(N)                                                  \
+  case N:                                                     \
+    *col = cols_blocks<N>(p);                                 \
+    break;
+    PAT_SIZE_CASES(X)
+#undef X
+    default: return PAT_EUNSUPPORTED;
+  }
+  return PAT_OK;
+}
+
+BatchSlot make_slot(const BatchProb& b) {
+  const pat_plan* p = b.pr.plan;
+  const pat_grid& g = p->g;
+  const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
+  BatchSlot s{};
+  s.tb = p->tb;
+  s.c = b.pr.c;
+  s.ux = b.f.ux; s.uy = b.f.uy; s.rx = b.f.rx; s.ry = b.f.ry;
+  s.SA = b.f.SA; s.SB = b.f.SB;
+  s.hist_base = b.f.hist_base;
+  s.dpart = b.f.dpart;
+  s.resid = b.a.resid;
+  s.uhx = b.a.uhx; s.uhy = b.a.uhy; s.rhx = b.a.rhx; s.rhy = b.a.rhy; s.gck = b.a.gck;
+  s.SC = b.a.SC; s.SD = b.a.SD;
+  s.ctl = b.f.ctl;
+  s.sc_grad = (float)(g.dt / g.rho0 * nrm);
+  s.sc_div = (float)(g.dt * g.rho0 * nrm);
+  return s;
+}
+
+// Slot tables of an active set (members in class order) appended to ctx->host.
+void add_tables(BatchContext* ctx, const BatchClass& cl, const std::vector<int>& active, BatchEpoch& e) {
+  e.col.off = e.row.off = ctx->host.size();
+  e.col.n = e.row.n = (int)active.size();
+  int bc = 0, br = 0;
+  for (int i : active) {
+    BatchSlot s = make_slot(ctx->probs[i]);
+    s.b_col = bc;
+    s.b_row = br;
+    s.b_adj = br;
+    bc += ctx->probs[i].col;
+    br += ctx->probs[i].row;
+    ctx->host.push_back(s);
+  }
+  e.col.blocks = bc;
+  e.row.blocks = br;
+  e.adj.clear();
+  if (!cl.fast) {                   // one adjoint-density launch over the row slots
+    SlotRange r = e.row;
+    e.adj.push_back(r);
+    return;
+  }
+  for (int kb : {1, 2, 4, 8}) {     // one launch per block shape
+    SlotRange r;
+    r.off = ctx->host.size();
+    r.kb = kb;
+    int ba = 0;
+    for (int i : active) {
+      if (ctx->probs[i].pr.plan->kb != kb) continue;
+      BatchSlot s = make_slot(ctx->probs[i]);
+      s.b_adj = ba;
+      ba += ctx->probs[i].adj;
+      ctx->host.push_back(s);
+      ++r.n;
+    }
+    r.blocks = ba;
+    if (r.n) e.adj.push_back(r);
+  }
+}
+
+int batch_build(BatchContext* ctx, int32_t nprob, const pat_problem* probs, int nstreams) {
+  ctx->probs.resize((size_t)nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const pat_problem& pr = probs[i];
+    BatchProb& b = ctx->probs[i];
+    b.pr = pr;
+    pat_plan* p = pr.plan;
+    b.L = make_layout(p, 0);
+    if (pr.ws_bytes < b.L.total) return PAT_EWORKSPACE;
+    void* ws = pr.ws;
+    b.f.c = pr.c;
+    b.f.ux = at<float>(ws, b.L.ux); b.f.uy = at<float>(ws, b.L.uy);
+    b.f.rx = at<float>(ws, b.L.rx); b.f.ry = at<float>(ws, b.L.ry);
+    b.f.SA = at<float2>(ws, b.L.SA); b.f.SB = at<float2>(ws, b.L.SB);
+    b.f.hist_base = at<float>(ws, b.L.hist);
+    b.f.dpart = at<float>(ws, b.L.dpart);
+    b.f.ctl = at<StepCtl>(ws, b.L.ctl);
+    b.a.c = pr.c;
+    b.a.hist_base = b.f.hist_base;
+    b.a.resid = pr.resid;
+    b.a.uhx = at<float>(ws, b.L.uhx); b.a.uhy = at<float>(ws, b.L.uhy);
+    b.a.rhx = at<float>(ws, b.L.rhx); b.a.rhy = at<float>(ws, b.L.rhy); b.a.gck = at<float>(ws, b.L.gck);
+    b.a.SC = at<float2>(ws, b.L.SC); b.a.SD = at<float2>(ws, b.L.SD);
+    b.a.ctl = b.f.ctl;
+    b.steps = p->g.nt - 1;
+    PAT_TRY(launch_blocks(p, &b.col, &b.row, &b.adj));
+  }
+  // classes: same family and grid size, in order of first appearance
+  for (int i = 0; i < nprob; ++i) {
+    const pat_plan* p = ctx->probs[i].pr.plan;
+    BatchClass* cl = nullptr;
+    for (auto& c : ctx->classes)
+      if (c.nx == p->g.nx && c.ny == p->g.ny && c.fast == p->fast) cl = &c;
+    if (!cl) {
+      ctx->classes.emplace_back();
+      cl = &ctx->classes.back();
+      cl->nx = p->g.nx;
+      cl->ny = p->g.ny;
+      cl->fast = p->fast;
+    }
+    cl->members.push_back(i);
+    cl->T = std::max(cl->T, ctx->probs[i].steps);
+  }
+  // the classes with the most work get their own streams first
+  std::vector<double> work(ctx->classes.size(), 0.0);
+  for (size_t c = 0; c < ctx->classes.size(); ++c)
+    for (int i : ctx->classes[c].members) {
+      const pat_plan* p = ctx->probs[i].pr.plan;
+      work[c] += (double)p->K * p->g.nx * p->g.ny * p->g.nt;
+    }
+  std::vector<int> order(ctx->classes.size());
+  for (size_t c = 0; c < order.size(); ++c) order[c] = (int)c;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<double> load((size_t)nstreams, 0.0);
+  for (int c : order) {
+    const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    ctx->classes[c].stream = s;
+    load[s] += work[c];
+  }
+  // epochs and their slot tables
+  for (auto& cl : ctx->classes) {
+    std::vector<int> bounds;
+    for (int i : cl.members) {
+      if (ctx->probs[i].steps == 0) cl.no_steps.push_back(i);
+      else bounds.push_back(cl.T - ctx->probs[i].steps);
+    }
+    bounds.push_back(cl.T);
+    std::sort(bounds.begin(), bounds.end());
+    bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
+    for (size_t k = 0; k + 1 < bounds.size(); ++k) {
+      BatchEpoch e;
+      e.begin = bounds[k];
+      e.end = bounds[k + 1];
+      std::vector<int> active;
+      for (int i : cl.members) {
+        const int st = ctx->probs[i].steps;
+        if (st == 0) continue;
+        if (cl.T - st <= e.begin) active.push_back(i);
+        if (cl.T - st == e.begin) e.starting.push_back(i);
+      }
+      add_tables(ctx, cl, active, e);
+      cl.fwd.push_back(std::move(e));
+    }
+    bounds.assign(1, 0);
+    for (int i : cl.members)
+      if (ctx->probs[i].steps > 0) bounds.push_back(ctx->probs[i].steps);
+    std::sort(bounds.begin(), bounds.end());
+    bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
+    for (size_t k = 0; k + 1 < bounds.size(); ++k) {
+      BatchEpoch e;
+      e.begin = bounds[k];
+      e.end = bounds[k + 1];
+      std::vector<int> active;
+      for (int i : cl.members) {
+        const int st = ctx->probs[i].steps;
+        if (st >= e.end) active.push_back(i);
+        if (st == e.end) e.ending.push_back(i);
+      }
+      add_tables(ctx, cl, active, e);
+      cl.adj.push_back(std::move(e));
+    }
+  }
+  if (!ctx->host.empty()) {
+    const size_t bytes = ctx->host.size() * sizeof(BatchSlot);
+    if (hipMalloc(&ctx->dev, bytes) != hipSuccess) return PAT_EHIP;
+    if (hipMemcpy(ctx->dev, ctx->host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return PAT_EHIP;
+  }
+  return PAT_OK;
+}
+
+// `count` steps of an epoch, launched directly.
+int batch_steps(const BatchContext* ctx, const BatchClass& cl, const BatchEpoch& e, bool fwd, int count,
+                hipStream_t st) {
+  for (int i = 0; i < count; ++i) {
+    const BatchSlot* sc = ctx->dev + e.col.off;
+    const BatchSlot* sr = ctx->dev + e.row.off;
+    if (fwd) {
+      PAT_TRY(batch_launch_col(COL_GRAD1, cl.fast, cl.ny, sc, e.col.n, e.col.blocks, st));
+      PAT_TRY(batch_launch_row(BK_FWD_U, cl.fast, cl.nx, sr, e.row.n, e.row.blocks, st));
+      PAT_TRY(batch_launch_col(COL_PAIRM, cl.fast, cl.ny, sc, e.col.n, e.col.blocks, st));
+      PAT_TRY(batch_launch_row(BK_FWD_RHO, cl.fast, cl.nx, sr, e.row.n, e.row.blocks, st));
+    } else {
+      PAT_TRY(batch_launch_col(COL_SUMM, cl.fast, cl.ny, sc, e.col.n, e.col.blocks, st));
+      for (const auto& r : e.adj)
+        PAT_TRY(batch_launch_adj_rho(cl.fast, cl.nx, r.kb, ctx->dev + r.off, r.n, r.blocks, st));
+      PAT_TRY(batch_launch_col(COL_PAIRP, cl.fast, cl.ny, sc, e.col.n, e.col.blocks, st));
+      PAT_TRY(batch_launch_row(BK_ADJ_U, cl.fast, cl.nx, sr, e.row.n, e.row.blocks, st));
+    }
+  }
+  return PAT_OK;
+}
+
+// Enqueue `count` steps of an epoch: replay its captured graph (captured on
+// first use), or launch directly for a single step or without graphs.
+int batch_run(BatchContext* ctx, const BatchClass& cl, const BatchEpoch& e, bool fwd, int count, hipStream_t st) {
+  if (count <= 0) return PAT_OK;
+  if (count == 1 || !graphs_enabled()) return batch_steps(ctx, cl, e, fwd, count, st);
+  uint64_t key = 1469598103934665603ull;
+  const void* idents[3] = {&cl, &e, nullptr};
+  key = fnv(key, idents, sizeof(idents));
+  key = fnv(key, &fwd, sizeof(fwd));
+  key = fnv(key, &count, sizeof(count));
+  for (auto& g : ctx->graphs)
+    if (g.key == key) {
+      if (hipGraphLaunch(g.exec, st) != hipSuccess) return PAT_EHIP;
+      return hipEventRecord(g.done, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+    }
+  if (!ctx->cap && hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) return PAT_EHIP;
+  if (hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PAT_EHIP;
+  const int sb = batch_steps(ctx, cl, e, fwd, count, ctx->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(ctx->cap, &graph);
+  if (sb != PAT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return sb;
+  }
+  if (ee != hipSuccess || !graph) return PAT_EHIP;
+  BatchGraph g{key, nullptr, nullptr};
+  const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return PAT_EHIP;
+  if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGraphExecDestroy(g.exec);
+    return PAT_EHIP;
+  }
+  ctx->graphs.push_back(g);
+  if (hipGraphLaunch(g.exec, st) != hipSuccess) return PAT_EHIP;
+  return hipEventRecord(g.done, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+int batch_fwd_init(const BatchProb& b, hipStream_t st) {
+  PAT_TRY(set_ctl(st, b.f.ctl, 1 | 4, -1, 0, 0));
+  return launch_fwd_init(b.pr.plan, st, b.pr.c, b.pr.p0, b.f.rx, b.f.ry, b.f.hist_base, b.f.dpart, b.f.SA);
+}
+
+// Between the two solves: traces, misfit and J, adjoint state at zero.
+int batch_middle(const BatchProb& b, hipStream_t st) {
+  const pat_plan* p = b.pr.plan;
+  const pat_grid& g = p->g;
+  const int64_t rows = (int64_t)p->K * g.nt;
+  hipLaunchKernelGGL(k_sensor_finalize, dim3(grid_blocks(rows * p->m)), dim3(256), 0, st, b.f.dpart, b.pr.data,
+                     rows, p->m);
+  PAT_TRY(last_error());
+  const int64_t per_k = (int64_t)g.nt * p->m;
+  hipLaunchKernelGGL(k_misfit, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, b.pr.data, b.pr.y, b.pr.w, b.pr.resid,
+                     p->red, per_k, p->K);
+  PAT_TRY(last_error());
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, st, p->red, RED_BLOCKS, b.pr.J, 0.5);
+  PAT_TRY(last_error());
+  PAT_TRY(fill_zero(st, b.a.uhx, b.L.F));
+  PAT_TRY(fill_zero(st, b.a.uhy, b.L.F));
+  PAT_TRY(fill_zero(st, b.a.rhx, b.L.F));
+  PAT_TRY(fill_zero(st, b.a.rhy, b.L.F));
+  PAT_TRY(fill_zero(st, b.a.gck, b.L.F));
+  PAT_TRY(fill_zero(st, b.a.SC, b.L.Sp));
+  PAT_TRY(fill_zero(st, b.a.SD, b.L.Sp));
+  return set_ctl(st, b.a.ctl, 2 | 4, 0, g.nt, 0);
+}
+
+// Closing terms of the adjoint: g_p0 and the initial-state part of g_c.
+int batch_closing(const BatchProb& b, hipStream_t st) {
+  const pat_plan* p = b.pr.plan;
+  const pat_grid& g = p->g;
+  const double nrm = 1.0 / ((double)g.nx * (double)g.ny);
+  PAT_TRY(launch_col<COL_SUMM>(p, st, b.a.SC, b.a.SD, (float)(g.dt / g.rho0 * nrm), nullptr, 0));
+  PAT_TRY(launch_adj_final(p, st, b.pr.c, b.pr.p0, b.pr.resid, b.a.rhx, b.a.rhy, b.a.gck, b.pr.g_p0, b.a.SC));
+  const int64_t npix = (int64_t)g.ny * g.nx;
+  hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, b.a.gck, b.pr.g_c, p->gsl, npix);
+  return last_error();
+}
+
+// One class's whole evaluation on stream st.
+int batch_class(BatchContext* ctx, const BatchClass& cl, hipStream_t st) {
+  for (const auto& e : cl.fwd) {
+    for (int i : e.starting) PAT_TRY(batch_fwd_init(ctx->probs[i], st));
+    for (int n = e.begin; n < e.end;) {
+      const int cnt = std::min(kChunk, e.end - n);
+      PAT_TRY(batch_run(ctx, cl, e, true, cnt, st));
+      n += cnt;
+    }
+  }
+  for (int i : cl.no_steps) PAT_TRY(batch_fwd_init(ctx->probs[i], st));
+  for (int i : cl.members) PAT_TRY(batch_middle(ctx->probs[i], st));
+  for (int i : cl.no_steps) PAT_TRY(batch_closing(ctx->probs[i], st));
+  for (const auto& e : cl.adj) {
+    for (int n = e.begin; n < e.end;) {
+      const int cnt = std::min(kChunk, e.end - n);
+      PAT_TRY(batch_run(ctx, cl, e, false, cnt, st));
+      n += cnt;
+    }
+    for (int i : e.ending) PAT_TRY(batch_closing(ctx->probs[i], st));
+  }
+  return PAT_OK;
 }
 
 }  // namespace
@@ -838,6 +1206,7 @@ const char* pat_status_string(int s) {
     case PAT_EUNSUPPORTED: return "unsupported size";
     case PAT_EWORKSPACE: return "workspace too small or not filled by a recording pat_forward";
     case PAT_EHIP: return "HIP runtime error";
+    case PAT_ENONFINITE: return "non-finite value in an output (check mode)";
     default: return "unknown status";
   }
 }
@@ -941,6 +1310,7 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   size_t i_srs = add(srs.data(), srs.size() * 4), i_spix = add(spix.data(), spix.size() * sizeof(ScatterPix));
   size_t i_stap = add(stap.data(), stap.size() * sizeof(ScatterTap));
   size_t i_red = add(nullptr, RED_BLOCKS * sizeof(double));
+  size_t i_flag = add(nullptr, sizeof(int32_t));
 
   pat_plan* p = new (std::nothrow) pat_plan();
   if (!p) return PAT_EHIP;
@@ -949,7 +1319,6 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   p->m = m;
   p->nh = nh;
   p->fast = fast_size(nx) && fast_size(ny) && !std::getenv("PAT_GENERIC_KERNELS");
-  p->col_seq = std::getenv("PAT_COL_SEQ") != nullptr;
   p->nhs = p->fast ? nx / 2 : nh;
   // 4 datasets per block: g_c traffic 2 B/pt instead of 8; 8 per block (one
   // block per CU at 107 KB of LDS) measured no faster at 512^2 x 8
@@ -983,6 +1352,8 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   t.s_tap = (const ScatterTap*)P(i_stap);
   t.nx = nx; t.ny = ny; t.nh = nh; t.K = K; t.m = m; t.nt = g->nt;
   p->red = (double*)P(i_red);
+  p->flag = (int32_t*)P(i_flag);
+  p->check_finite = std::getenv("PAT_CHECK_FINITE") != nullptr;
   *out = p;
   return PAT_OK;
 }
@@ -1050,6 +1421,7 @@ int pat_forward(pat_plan* p, const float* c, const float* p0, float* data, void*
     p->rec_p0 = p0;
     p->rec_ckpt = ckpt_every;
   }
+  if (p->check_finite) return check_outputs(p, st, {{data, rows * p->m}});
   return PAT_OK;
 }
 
@@ -1142,7 +1514,9 @@ int pat_adjoint_gradient(pat_plan* p, const float* c, const float* p0, const flo
   PAT_TRY(launch_adj_final(p, st, c, p0, resid, a.rhx, a.rhy, a.gck, g_p0, a.SC));
   const int64_t npix = (int64_t)g.ny * g.nx;
   hipLaunchKernelGGL(k_reduce_k, dim3(grid_blocks(npix)), dim3(256), 0, st, a.gck, g_c, p->gsl, npix);
-  return last_error();
+  PAT_TRY(last_error());
+  if (p->check_finite) return check_outputs(p, st, {{g_p0, (int64_t)p->K * npix}, {g_c, npix}});
+  return PAT_OK;
 }
 
 int pat_project_update(int64_t n, float* x, const float* d, float alpha, const float* lo, const float* hi,
@@ -1154,7 +1528,7 @@ int pat_project_update(int64_t n, float* x, const float* d, float alpha, const f
   return last_error();
 }
 
-int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, float* fine, int32_t nyf, int32_t nxf,
+int pat_prolong(int32_t nchan, const float* coarse, int32_t nxc, int32_t nyc, float* fine, int32_t nxf, int32_t nyf,
                 void* stream) {
   if (nchan <= 0 || nyc <= 0 || nxc <= 0 || nyf <= 0 || nxf <= 0 || !coarse || !fine) return PAT_EINVAL;
   const int64_t n = (int64_t)nchan * nyf * nxf;
@@ -1163,8 +1537,8 @@ int pat_prolong(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, fl
   return last_error();
 }
 
-int pat_prolong_phys(int32_t nchan, const float* coarse, int32_t nyc, int32_t nxc, double dxc, float* fine,
-                     int32_t nyf, int32_t nxf, double dxf, void* stream) {
+int pat_prolong_phys(int32_t nchan, const float* coarse, int32_t nxc, int32_t nyc, double dxc, float* fine,
+                     int32_t nxf, int32_t nyf, double dxf, void* stream) {
   if (nchan <= 0 || nyc <= 0 || nxc <= 0 || nyf <= 0 || nxf <= 0 || !coarse || !fine || !(dxc > 0.0) ||
       !(dxf > 0.0))
     return PAT_EINVAL;
@@ -1294,10 +1668,31 @@ int pat_plan_set_tile(pat_plan* p, int32_t col_tile) {
   return PAT_OK;
 }
 
+int pat_plan_set_col_order(pat_plan* p, int32_t sequential) {
+  if (!p || (sequential != 0 && sequential != 1)) return PAT_EINVAL;
+  if ((sequential != 0) != p->col_seq) {   // captured graphs hold the old kernels
+    drop_graphs(p);
+    p->col_seq = sequential != 0;
+  }
+  return PAT_OK;
+}
+
+int pat_batch_release(void) {
+  int status = PAT_OK;
+  batch_free(g_batch);
+  g_batch = nullptr;
+  for (hipStream_t s : g_pool) {
+    if (hipStreamSynchronize(s) != hipSuccess || hipStreamDestroy(s) != hipSuccess) status = PAT_EHIP;
+  }
+  g_pool.clear();
+  return status;
+}
+
 int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams, void* stream) {
   if (nprob <= 0 || !probs || nstreams <= 0 || nstreams > 16) return PAT_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  std::vector<BatchJob> jobs((size_t)nprob);
+  uint64_t sig = 1469598103934665603ull;
+  sig = fnv(sig, &nstreams, sizeof(nstreams));
   for (int i = 0; i < nprob; ++i) {
     const pat_problem& pr = probs[i];
     if (!pr.plan || !pr.c || !pr.p0 || !pr.y || !pr.w || !pr.data || !pr.resid || !pr.J || !pr.g_p0 || !pr.g_c ||
@@ -1305,42 +1700,31 @@ int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams
       return PAT_EINVAL;
     for (int j = 0; j < i; ++j)
       if (probs[j].plan == pr.plan || probs[j].ws == pr.ws) return PAT_EINVAL;   // one job per plan and workspace
-    BatchJob& jb = jobs[i];
-    jb.pr = pr;
-    pat_plan* p = pr.plan;
-    jb.L = make_layout(p, 0);
-    if (pr.ws_bytes < jb.L.total) return PAT_EWORKSPACE;
-    void* ws = pr.ws;
-    jb.f.c = pr.c;
-    jb.f.ux = at<float>(ws, jb.L.ux); jb.f.uy = at<float>(ws, jb.L.uy);
-    jb.f.rx = at<float>(ws, jb.L.rx); jb.f.ry = at<float>(ws, jb.L.ry);
-    jb.f.SA = at<float2>(ws, jb.L.SA); jb.f.SB = at<float2>(ws, jb.L.SB);
-    jb.f.hist_base = at<float>(ws, jb.L.hist);
-    jb.f.dpart = at<float>(ws, jb.L.dpart);
-    jb.f.ctl = at<StepCtl>(ws, jb.L.ctl);
-    jb.a.c = pr.c;
-    jb.a.hist_base = jb.f.hist_base;
-    jb.a.resid = pr.resid;
-    jb.a.uhx = at<float>(ws, jb.L.uhx); jb.a.uhy = at<float>(ws, jb.L.uhy);
-    jb.a.rhx = at<float>(ws, jb.L.rhx); jb.a.rhy = at<float>(ws, jb.L.rhy); jb.a.gck = at<float>(ws, jb.L.gck);
-    jb.a.SC = at<float2>(ws, jb.L.SC); jb.a.SD = at<float2>(ws, jb.L.SD);
-    jb.a.ctl = jb.f.ctl;
-    jb.cost = (double)p->K * p->g.nx * p->g.ny * p->g.nt;
+    if (pr.ws_bytes < make_layout(pr.plan, 0).total) return PAT_EWORKSPACE;
+    sig = fnv(sig, &pr, sizeof(pr));
+    sig = fnv(sig, &pr.plan->tb, sizeof(Tables));
+    sig = fnv(sig, &pr.plan->g, sizeof(pat_grid));
+    const int shape[3] = {pr.plan->K, pr.plan->kb, pr.plan->fast ? 1 : 0};
+    sig = fnv(sig, shape, sizeof(shape));
   }
-  for (auto& jb : jobs) jb.pr.plan->recorded = false;   // the batch overwrites every workspace
-  const int ns = std::min(nstreams, nprob);
+  if (!g_batch || g_batch->sig != sig) {   // a new set of problems: new slot tables and graphs
+    batch_free(g_batch);
+    g_batch = new (std::nothrow) BatchContext();
+    if (!g_batch) return PAT_EHIP;
+    g_batch->sig = sig;
+    const int sb = batch_build(g_batch, nprob, probs, nstreams);
+    if (sb != PAT_OK) {
+      batch_free(g_batch);
+      g_batch = nullptr;
+      return sb;
+    }
+  }
+  BatchContext* ctx = g_batch;
+  for (auto& b : ctx->probs) b.pr.plan->recorded = false;   // the batch overwrites every workspace
+  int ns = 0;
+  for (const auto& cl : ctx->classes) ns = std::max(ns, cl.stream + 1);
   PAT_TRY(pool_streams(ns));
-  // schedule: longest problems first, each onto the least-loaded stream
-  std::vector<int> order((size_t)nprob);
-  for (int i = 0; i < nprob; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return jobs[x].cost > jobs[y].cost; });
-  std::vector<double> load((size_t)ns, 0.0);
-  for (int i : order) {
-    const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    jobs[i].stream = s;
-    load[s] += jobs[i].cost;
-  }
-  // fork: every internal stream waits for the work already queued on the caller's stream
+  // fork: every class stream waits for the work already queued on the caller's stream
   hipEvent_t fork;
   if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return PAT_EHIP;
   std::vector<hipEvent_t> done((size_t)ns, nullptr);
@@ -1348,19 +1732,11 @@ int pat_batch_gradient(int32_t nprob, const pat_problem* probs, int32_t nstreams
   if (hipEventRecord(fork, st) != hipSuccess) status = PAT_EHIP;
   for (int s = 0; s < ns && status == PAT_OK; ++s)
     if (hipStreamWaitEvent(g_pool[s], fork, 0) != hipSuccess) status = PAT_EHIP;
-  // round robin over the problems, one unit each, until all are done
-  bool left = true;
-  while (status == PAT_OK && left) {
-    left = false;
-    for (int i : order) {
-      BatchJob& jb = jobs[i];
-      if (jb.phase >= 5) continue;
-      status = job_unit(jb, g_pool[jb.stream]);
-      if (status != PAT_OK) break;
-      left = left || jb.phase < 5;
-    }
+  for (const auto& cl : ctx->classes) {
+    if (status != PAT_OK) break;
+    status = batch_class(ctx, cl, g_pool[cl.stream]);
   }
-  // join: the caller's stream waits for every internal stream
+  // join: the caller's stream waits for every class stream
   for (int s = 0; s < ns; ++s) {
     if (hipEventCreateWithFlags(&done[s], hipEventDisableTiming) != hipSuccess) {
       status = PAT_EHIP;

@@ -47,6 +47,18 @@ __global__ void k_set_ctl(int32_t* __restrict__ ctl, int mask, int fwd_n, int ad
   if (mask & 4) ctl[2] = hist_first;
 }
 
+__global__ void k_set_flag(int32_t* __restrict__ flag, int32_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = v;
+}
+
+// flag = 1 if any x[i] is NaN or infinite (every writer writes the same value)
+__global__ void k_flag_nonfinite(const float* __restrict__ x, int64_t n, int32_t* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(x[i]);
+  if (bad) flag[0] = 1;
+}
+
 __global__ void k_fill_zero(float* __restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = 0.f;

@@ -154,15 +154,15 @@ __device__ __forceinline__ void scatter_rows(const Tables& tb, float* PH, int y0
 
 // n = 0: p = p0, rho_x = rho_y = p0 / (2 c^2), sensors, history, row spectra of p0.
 template <int NX>
-__global__ __launch_bounds__(256) void k_fwd_init(Tables tb, const float* __restrict__ c,
-                                                  const float* __restrict__ p0, float* __restrict__ rx,
-                                                  float* __restrict__ ry, float* __restrict__ hist0,
-                                                  float* __restrict__ dpart, float2* __restrict__ SA) {
+__device__ __forceinline__ void k_fwd_init_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                                const float* __restrict__ p0, float* __restrict__ rx,
+                                                float* __restrict__ ry, float* __restrict__ hist0,
+                                                float* __restrict__ dpart, float2* __restrict__ SA) {
   using C = RowCfg<NX>;
   __shared__ float2 Z[C::ROWS / 2][C::PITCH];
   __shared__ float P[C::ROWS][NX];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
-  const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
+  const int k = bid % K, y0 = (bid / K) * C::ROWS;
   const int tid = threadIdx.x, r = tid / C::T, q = tid % C::T, y = y0 + r;
   const size_t fk = (size_t)k * ny * NX;
   if (y < ny) {
@@ -195,16 +195,24 @@ __global__ __launch_bounds__(256) void k_fwd_init(Tables tb, const float* __rest
   }
 }
 
+template <int NX>
+__global__ __launch_bounds__(256) void k_fwd_init(Tables tb, const float* __restrict__ c,
+                                                  const float* __restrict__ p0, float* __restrict__ rx,
+                                                  float* __restrict__ ry, float* __restrict__ hist0,
+                                                  float* __restrict__ dpart, float2* __restrict__ SA) {
+  pat::k_fwd_init_body<NX>(blockIdx.x, tb, c, p0, rx, ry, hist0, dpart, SA);
+}
+
 // Velocity update.  first != 0: u^{-1/2} = dt/(2 rho0) D+ p0 = G/2 (eq. (1): p_t(0) = 0).
 template <int NX>
-__global__ __launch_bounds__(256) void k_fwd_u(Tables tb, float* __restrict__ ux, float* __restrict__ uy,
-                                               float2* __restrict__ SA, float2* __restrict__ SB,
-                                               const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_fwd_u_body(const int bid, const Tables& tb, float* __restrict__ ux,
+                                             float* __restrict__ uy, float2* __restrict__ SA, float2* __restrict__ SB,
+                                             const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
   const int first = ctl->fwd_n == 0;
   __shared__ float2 Z[C::ROWS][C::PITCH];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
-  const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
+  const int k = bid % K, y0 = (bid / K) * C::ROWS;
   const int tid = threadIdx.x, r = tid / C::T, q = tid % C::T, y = y0 + r;
   const bool ok = y < ny;
   const size_t srow = ((size_t)k * ny + (ok ? y : 0)) * nh;
@@ -239,12 +247,20 @@ __global__ __launch_bounds__(256) void k_fwd_u(Tables tb, float* __restrict__ ux
   }
 }
 
+template <int NX>
+__global__ __launch_bounds__(256) void k_fwd_u(Tables tb, float* __restrict__ ux, float* __restrict__ uy,
+                                               float2* __restrict__ SA, float2* __restrict__ SB,
+                                               const StepCtl* __restrict__ ctl) {
+  pat::k_fwd_u_body<NX>(blockIdx.x, tb, ux, uy, SA, SB, ctl);
+}
+
 // Density / pressure update, sensors at time level n+1, history, row spectra of p.
 template <int NX>
-__global__ __launch_bounds__(256) void k_fwd_rho(Tables tb, const float* __restrict__ c, float* __restrict__ rx,
-                                                 float* __restrict__ ry, float* __restrict__ hist_base,
-                                                 float* __restrict__ dpart, float2* __restrict__ SA,
-                                                 const float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                               float* __restrict__ rx, float* __restrict__ ry,
+                                               float* __restrict__ hist_base, float* __restrict__ dpart,
+                                               float2* __restrict__ SA, const float2* __restrict__ SB,
+                                               const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
   const int n = ctl->fwd_n;
   float* hist = hist_base ? hist_base + (size_t)(n + 1 - ctl->hist_first) * tb.K * tb.ny * NX : nullptr;
@@ -252,7 +268,7 @@ __global__ __launch_bounds__(256) void k_fwd_rho(Tables tb, const float* __restr
   __shared__ float2 Z[C::ROWS][C::PITCH];
   __shared__ float P[C::ROWS][NX];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
-  const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
+  const int k = bid % K, y0 = (bid / K) * C::ROWS;
   const int tid = threadIdx.x, r = tid / C::T, q = tid % C::T, y = y0 + r;
   const bool ok = y < ny;
   const size_t srow = ((size_t)k * ny + (ok ? y : 0)) * nh;
@@ -295,6 +311,14 @@ __global__ __launch_bounds__(256) void k_fwd_rho(Tables tb, const float* __restr
   }
 }
 
+template <int NX>
+__global__ __launch_bounds__(256) void k_fwd_rho(Tables tb, const float* __restrict__ c, float* __restrict__ rx,
+                                                 float* __restrict__ ry, float* __restrict__ hist_base,
+                                                 float* __restrict__ dpart, float2* __restrict__ SA,
+                                                 const float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
+  pat::k_fwd_rho_body<NX>(blockIdx.x, tb, c, rx, ry, hist_base, dpart, SA, SB, ctl);
+}
+
 // ===========================================================================
 // Column pass: forward column transforms, spectral multiplier, inverse.
 // ===========================================================================
@@ -306,15 +330,15 @@ enum ColMode : int {
 };
 
 template <int NY, int MODE>
-__global__ __launch_bounds__(ColCfg<NY>::BLOCK) void k_col(Tables tb, float2* __restrict__ SA,
-                                                           float2* __restrict__ SB, float scale,
-                                                           int32_t* __restrict__ step, int32_t delta) {
+__device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, float2* __restrict__ SA,
+                                           float2* __restrict__ SB, float scale, int32_t* __restrict__ step,
+                                           int32_t delta) {
   using C = ColCfg<NY>;
-  if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += delta;   // first pass of a step
+  if (step && bid == 0 && threadIdx.x == 0) *step += delta;   // first pass of a step
   __shared__ float2 A[C::TC][C::PITCH];
   __shared__ float2 B[C::TC][C::PITCH];
   const int K = tb.K, nh = tb.nh;
-  const int k = blockIdx.x % K, c0 = (blockIdx.x / K) * C::TC;
+  const int k = bid % K, c0 = (bid / K) * C::TC;
   const int tid = threadIdx.x;
   const size_t base = (size_t)k * NY * nh;
   constexpr bool TWO_IN = MODE != COL_GRAD1;
@@ -369,6 +393,13 @@ __global__ __launch_bounds__(ColCfg<NY>::BLOCK) void k_col(Tables tb, float2* __
   }
 }
 
+template <int NY, int MODE>
+__global__ __launch_bounds__(ColCfg<NY>::BLOCK) void k_col(Tables tb, float2* __restrict__ SA,
+                                                           float2* __restrict__ SB, float scale,
+                                                           int32_t* __restrict__ step, int32_t delta) {
+  pat::k_col_body<NY, MODE>(blockIdx.x, tb, SA, SB, scale, step, delta);
+}
+
 // ===========================================================================
 // Adjoint passes (exact transpose of the forward recurrence, run backwards)
 // ===========================================================================
@@ -376,11 +407,11 @@ __global__ __launch_bounds__(ColCfg<NY>::BLOCK) void k_col(Tables tb, float2* __
 // ph = S^T r^n + (inverse rows of the SUMM spectrum); rh += c^2 ph;
 // gc += (2/c) p^n ph; spectra of (a_x rh_x, a_y rh_y); then rh <- a^2 rh.
 template <int NX>
-__global__ __launch_bounds__(256) void k_adj_rho(Tables tb, const float* __restrict__ c,
-                                                 const float* __restrict__ hist_base, const float* __restrict__ resid,
-                                                 float* __restrict__ rhx, float* __restrict__ rhy,
-                                                 float* __restrict__ gck, float2* __restrict__ SA,
-                                                 float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                               const float* __restrict__ hist_base, const float* __restrict__ resid,
+                                               float* __restrict__ rhx, float* __restrict__ rhy,
+                                               float* __restrict__ gck, float2* __restrict__ SA,
+                                               float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
   const int n = ctl->adj_n;
   const float* p_n = hist_base + (size_t)(n - ctl->hist_first) * tb.K * tb.ny * NX;
@@ -388,7 +419,7 @@ __global__ __launch_bounds__(256) void k_adj_rho(Tables tb, const float* __restr
   __shared__ float2 Z[C::ROWS][C::PITCH];
   __shared__ float PH[C::ROWS][NX];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
-  const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
+  const int k = bid % K, y0 = (bid / K) * C::ROWS;
   const int tid = threadIdx.x;
   constexpr int T2 = 2 * C::T;
   {
@@ -449,17 +480,26 @@ __global__ __launch_bounds__(256) void k_adj_rho(Tables tb, const float* __restr
   }
 }
 
+template <int NX>
+__global__ __launch_bounds__(256) void k_adj_rho(Tables tb, const float* __restrict__ c,
+                                                 const float* __restrict__ hist_base, const float* __restrict__ resid,
+                                                 float* __restrict__ rhx, float* __restrict__ rhy,
+                                                 float* __restrict__ gck, float2* __restrict__ SA,
+                                                 float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
+  pat::k_adj_rho_body<NX>(blockIdx.x, tb, c, hist_base, resid, rhx, rhy, gck, SA, SB, ctl);
+}
+
 // uh <- as^2 uh + (inverse rows of the PAIRP spectra); spectra of (w_x uh_x, w_y uh_y)
 // with w = as (next step) or as - as^2/2 (closing term, at adjoint step n = 1).
 template <int NX>
-__global__ __launch_bounds__(256) void k_adj_u(Tables tb, float* __restrict__ uhx, float* __restrict__ uhy,
-                                               float2* __restrict__ SA, float2* __restrict__ SB,
-                                               const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void k_adj_u_body(const int bid, const Tables& tb, float* __restrict__ uhx,
+                                             float* __restrict__ uhy, float2* __restrict__ SA,
+                                             float2* __restrict__ SB, const StepCtl* __restrict__ ctl) {
   using C = RowCfg<NX>;
   const int final_ = ctl->adj_n == 1;
   __shared__ float2 Z[C::ROWS][C::PITCH];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
-  const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
+  const int k = bid % K, y0 = (bid / K) * C::ROWS;
   const int tid = threadIdx.x, r = tid / C::T, q = tid % C::T, y = y0 + r;
   const bool ok = y < ny;
   const size_t srow = ((size_t)k * ny + (ok ? y : 0)) * nh;
@@ -493,19 +533,26 @@ __global__ __launch_bounds__(256) void k_adj_u(Tables tb, float* __restrict__ uh
   }
 }
 
+template <int NX>
+__global__ __launch_bounds__(256) void k_adj_u(Tables tb, float* __restrict__ uhx, float* __restrict__ uhy,
+                                               float2* __restrict__ SA, float2* __restrict__ SB,
+                                               const StepCtl* __restrict__ ctl) {
+  pat::k_adj_u_body<NX>(blockIdx.x, tb, uhx, uhy, SA, SB, ctl);
+}
+
 // Closing terms: g_p0 = S^T r^0 + (inverse rows of SUMM spectrum of
 // (as - as^2/2) uh) + (rh_x + rh_y) / (2 c^2);  gc += -(p0 / c^3)(rh_x + rh_y).
 template <int NX>
-__global__ __launch_bounds__(256) void k_adj_final(Tables tb, const float* __restrict__ c,
-                                                   const float* __restrict__ p0, const float* __restrict__ resid0,
-                                                   const float* __restrict__ rhx, const float* __restrict__ rhy,
-                                                   float* __restrict__ gck, float* __restrict__ gp0,
-                                                   const float2* __restrict__ SA) {
+__device__ __forceinline__ void k_adj_final_body(const int bid, const Tables& tb, const float* __restrict__ c,
+                                                 const float* __restrict__ p0, const float* __restrict__ resid0,
+                                                 const float* __restrict__ rhx, const float* __restrict__ rhy,
+                                                 float* __restrict__ gck, float* __restrict__ gp0,
+                                                 const float2* __restrict__ SA) {
   using C = RowCfg<NX>;
   __shared__ float2 Z[C::ROWS / 2][C::PITCH];
   __shared__ float PH[C::ROWS][NX];
   const int K = tb.K, ny = tb.ny, nh = tb.nh;
-  const int k = blockIdx.x % K, y0 = (blockIdx.x / K) * C::ROWS;
+  const int k = bid % K, y0 = (bid / K) * C::ROWS;
   const int tid = threadIdx.x;
   constexpr int T2 = 2 * C::T;
   {
@@ -546,6 +593,15 @@ __global__ __launch_bounds__(256) void k_adj_final(Tables tb, const float* __res
       gck[f + x] += -(p0[f + x] / (cc * cc * cc)) * rs;
     }
   }
+}
+
+template <int NX>
+__global__ __launch_bounds__(256) void k_adj_final(Tables tb, const float* __restrict__ c,
+                                                   const float* __restrict__ p0, const float* __restrict__ resid0,
+                                                   const float* __restrict__ rhx, const float* __restrict__ rhy,
+                                                   float* __restrict__ gck, float* __restrict__ gp0,
+                                                   const float2* __restrict__ SA) {
+  pat::k_adj_final_body<NX>(blockIdx.x, tb, c, p0, resid0, rhx, rhy, gck, gp0, SA);
 }
 
 }  // namespace pat

@@ -16,13 +16,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpat.so")
 
-PAT_OK, PAT_EINVAL, PAT_EUNSUPPORTED, PAT_EWORKSPACE, PAT_EHIP = 0, -1, -2, -3, -4
+PAT_OK, PAT_EINVAL, PAT_EUNSUPPORTED, PAT_EWORKSPACE, PAT_EHIP, PAT_ENONFINITE = 0, -1, -2, -3, -4, -5
 
 EXPORTS = (
     "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_history_field", "pat_misfit",
     "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_prolong_phys", "pat_time_interp",
     "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_lbfgs_direction_noalloc", "pat_dot", "pat_status_string",
-    "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_batch_gradient",
+    "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_plan_set_col_order",
+    "pat_batch_gradient",
+    "pat_batch_release",
     "pat_ou_create", "pat_ou_destroy", "pat_ou_scratch_bytes", "pat_ou_apply", "pat_ou_prior",
 )
 
@@ -85,7 +87,9 @@ def lib() -> ctypes.CDLL:
     L.pat_trace_stop.argtypes = []
     L.pat_trace_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
     L.pat_plan_set_tile.argtypes = [vp, i32]
+    L.pat_plan_set_col_order.argtypes = [vp, i32]
     L.pat_batch_gradient.argtypes = [i32, vp, i32, vp]
+    L.pat_batch_release.argtypes = []
     L.pat_ou_create.argtypes = [i32, i32, f64, f64, vp, ctypes.POINTER(vp)]
     L.pat_ou_destroy.argtypes = [vp]
     L.pat_ou_scratch_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
@@ -179,6 +183,10 @@ class Plan:
         """Column-pass tile width (0 = default, 8); results do not change."""
         _check(lib().pat_plan_set_tile(self._h, int(col_tile)), "pat_plan_set_tile")
 
+    def set_col_order(self, sequential: int):
+        """Column-pass transform order (0 = together, 1 = one after the other); results do not change."""
+        _check(lib().pat_plan_set_col_order(self._h, int(sequential)), "pat_plan_set_col_order")
+
     def workspace_size(self, ckpt_every: int = 0) -> int:
         b = ctypes.c_size_t()
         _check(lib().pat_workspace_size(self._h, int(ckpt_every), ctypes.byref(b)), "pat_workspace_size")
@@ -237,7 +245,7 @@ def prolong(coarse, fine):
     nchan2, nyf, nxf = fine.shape
     if nchan != nchan2:
         raise ValueError("channel mismatch")
-    _check(lib().pat_prolong(nchan, _f32(coarse), nyc, nxc, _f32(fine), nyf, nxf, _stream()), "pat_prolong")
+    _check(lib().pat_prolong(nchan, _f32(coarse), nxc, nyc, _f32(fine), nxf, nyf, _stream()), "pat_prolong")
 
 
 def prolong_phys(coarse, dx_coarse: float, fine, dx_fine: float):
@@ -247,7 +255,7 @@ def prolong_phys(coarse, dx_coarse: float, fine, dx_fine: float):
     nchan2, nyf, nxf = fine.shape
     if nchan != nchan2:
         raise ValueError("channel mismatch")
-    _check(lib().pat_prolong_phys(nchan, _f32(coarse), nyc, nxc, float(dx_coarse), _f32(fine), nyf, nxf,
+    _check(lib().pat_prolong_phys(nchan, _f32(coarse), nxc, nyc, float(dx_coarse), _f32(fine), nxf, nyf,
                                   float(dx_fine), _stream()), "pat_prolong_phys")
 
 
@@ -336,6 +344,11 @@ def batch_gradient(jobs, nstreams: int = 8):
         arr[i].ws_bytes = j["ws"].numel()
     _check(lib().pat_batch_gradient(len(jobs), ctypes.cast(arr, ctypes.c_void_p), int(nstreams), _stream()),
            "pat_batch_gradient")
+
+
+def batch_release():
+    """Destroy the library's internal batch streams (recreated by the next batch)."""
+    _check(lib().pat_batch_release(), "pat_batch_release")
 
 
 class OuPrior:

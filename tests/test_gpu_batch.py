@@ -1,7 +1,9 @@
 """Uneven batches and launch tuning (GPU): pat_batch_gradient gives every
 problem exactly the bits it gets alone, for problems of different grid sizes
 (power-of-two and mixed-radix), dataset counts and time axes, with any stream
-count; the column tile width changes no bit."""
+count; the column tile width changes no bit.  Problems of one transform
+family and grid size advance in shared launches (one launch per pass for
+all of them)."""
 import numpy as np
 import pytest
 
@@ -39,33 +41,54 @@ def _single(job):
     return {k: job[k].cpu().numpy().copy() for k in ("data", "resid", "J", "g_p0", "g_c")}
 
 
-def test_batch_equals_single_runs_bitwise():
+def _check_batch(jobs, ref, ns, what):
     import torch
     from paper_2505_08482_amd import pat
-    specs = [(128, 2, 120, 1), (192, 1, 90, 2), (256, 4, 70, 3), (64, 1, 150, 4), (128, 1, 41, 5)]
+    for j in jobs:
+        j["g_c"].fill_(7.0); j["g_p0"].fill_(7.0); j["data"].fill_(7.0); j["J"].fill_(7.0)
+    announce(f"batch nstreams={ns} {what}")
+    pat.batch_gradient(jobs, ns)
+    torch.cuda.synchronize()
+    for j, r in zip(jobs, ref):
+        for k in r:
+            assert np.array_equal(j[k].cpu().numpy(), r[k]), (ns, what, j["plan"].grid.nx, j["plan"].K, k)
+
+
+def test_batch_equals_single_runs_bitwise():
+    """Problems sharing launches (same family and grid size) with different
+    dataset counts (datasets per block of the adjoint density pass 1, 2, 4)
+    and time axes (the forward solves aligned at their ends, the adjoint
+    solves at their starts), including single-sample and two-sample problems;
+    batches replayed from their captured step graphs, and a different batch
+    in between (new slot tables)."""
+    from paper_2505_08482_amd import pat
+    specs = [(128, 2, 120, 1), (192, 1, 90, 2), (256, 4, 70, 3), (64, 1, 150, 4), (128, 1, 41, 5),
+             (128, 4, 77, 6), (192, 2, 2, 7), (128, 2, 1, 8), (192, 3, 131, 9)]
     jobs = [_job(*s) for s in specs]
     announce("single runs")
     ref = [_single(j) for j in jobs]
     for ns in (1, 3, 8):
-        for j in jobs:
-            j["g_c"].zero_(); j["g_p0"].zero_(); j["data"].zero_()
-        announce(f"batch nstreams={ns}")
-        pat.batch_gradient(jobs, ns)
-        torch.cuda.synchronize()
-        for j, r in zip(jobs, ref):
-            for k in r:
-                assert np.array_equal(j[k].cpu().numpy(), r[k]), (ns, j["plan"].grid.nx, k)
+        _check_batch(jobs, ref, ns, "first")
+    _check_batch(jobs, ref, 3, "again (replayed graphs)")
+    _check_batch(jobs[:4], ref[:4], 3, "another batch")
+    _check_batch(jobs, ref, 3, "the first batch again")
+    pat.batch_release()
+    _check_batch(jobs, ref, 2, "after releasing the streams")
     for j in jobs:
         j["plan"].close()
 
 
-def test_column_tile_changes_no_bit():
-    job = _job(256, 2, 80, 9)
-    announce("tile default")
-    a = _single(job)
-    job["plan"].set_tile(8)
-    announce("tile 8")
-    b = _single(job)
-    for k in a:
-        assert np.array_equal(a[k], b[k]), k
+@pytest.mark.parametrize("n, K", [(256, 2), (512, 8), (128, 3)])
+def test_column_launch_configuration_changes_no_bit(n, K):
+    """Every candidate of the tuner (column tile 4 or 8, the two transforms of
+    a thread together or one after the other) gives the same bits."""
+    job = _job(n, K, 60, 9)
+    announce(f"column configurations {n} K={K}")
+    ref = _single(job)
+    for tile, seq in ((8, 0), (0, 1), (8, 1)):
+        job["plan"].set_tile(tile)
+        job["plan"].set_col_order(seq)
+        out = _single(job)
+        for k in ref:
+            assert np.array_equal(ref[k], out[k]), (tile, seq, k)
     job["plan"].close()
