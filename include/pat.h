@@ -130,6 +130,20 @@ int pat_adjoint_gradient(pat_plan* plan, const float* c, const float* p0, const 
 int pat_project_update(int64_t n, float* x, const float* d, float alpha,
                        const float* lo, const float* hi, float lo_s, float hi_s, void* stream);
 
+/* Eq. (10)-(11): the free part of a vector for a projected step at x with
+ * gradient g: out_i = 0 where x_i sits on a bound with g pointing out of the
+ * box (x_i <= lo_i and g_i > 0, or x_i >= hi_i and g_i < 0), else v_i.  All
+ * arrays DEVICE [n]; out may alias v (not x or g). */
+int pat_free_part(int64_t n, const float* x, const float* g, const float* lo, const float* hi, const float* v,
+                  float* out, void* stream);
+
+/* Vector updates of the optimiser around Alg. 1 (step differences s = x+ - x,
+ * y = g+ - g, scaling): out = a x + b y (y may be NULL: out = a x), and
+ * out = x * s element-wise.  DEVICE arrays of n floats; out may alias the
+ * inputs. */
+int pat_axpby(int64_t n, float a, const float* x, float b, const float* y, float* out, void* stream);
+int pat_mul(int64_t n, const float* x, const float* s, float* out, void* stream);
+
 /* Sec. 3.1: bilinear interpolation of nchan coarse fields [nchan][nyc][nxc]
  * onto a finer grid [nchan][nyf][nxf] covering the same physical square
  * (cell-centred pixels), clamped at the border.  Each fine value is a convex
@@ -181,6 +195,10 @@ int pat_lbfgs_direction_noalloc(int64_t n, const float* g, int32_t npairs, const
  * (deterministic two-level reduction; `scratch` as for pat_lbfgs_direction
  * with npairs = 0). */
 int pat_dot(int64_t n, const float* a, const float* b, double* out, void* scratch, void* stream);
+
+/* max_i |x_i| of n floats into the DEVICE double *out (the steepest-descent
+ * normalisation of the first step; `scratch` as for pat_dot). */
+int pat_absmax(int64_t n, const float* x, double* out, void* scratch, void* stream);
 
 /* Column-pass tile width of a plan (power-of-two grids): 0 = the default for
  * the transform length, 8 = eight adjacent columns per block.  A tuning knob

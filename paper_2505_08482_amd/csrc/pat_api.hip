@@ -1528,6 +1528,27 @@ int pat_project_update(int64_t n, float* x, const float* d, float alpha, const f
   return last_error();
 }
 
+int pat_free_part(int64_t n, const float* x, const float* g, const float* lo, const float* hi, const float* v,
+                  float* out, void* stream) {
+  if (n <= 0 || !x || !g || !lo || !hi || !v || !out) return PAT_EINVAL;
+  hipLaunchKernelGGL(k_free_part, dim3(grid_blocks(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, x, g, lo,
+                     hi, v, out);
+  return last_error();
+}
+
+int pat_axpby(int64_t n, float a, const float* x, float b, const float* y, float* out, void* stream) {
+  if (n <= 0 || !x || !out) return PAT_EINVAL;
+  hipLaunchKernelGGL(k_axpby, dim3(grid_blocks(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, a, x, b, y,
+                     out);
+  return last_error();
+}
+
+int pat_mul(int64_t n, const float* x, const float* s, float* out, void* stream) {
+  if (n <= 0 || !x || !s || !out) return PAT_EINVAL;
+  hipLaunchKernelGGL(k_mul, dim3(grid_blocks(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, x, s, out);
+  return last_error();
+}
+
 int pat_prolong(int32_t nchan, const float* coarse, int32_t nxc, int32_t nyc, float* fine, int32_t nxf, int32_t nyf,
                 void* stream) {
   if (nchan <= 0 || nyc <= 0 || nxc <= 0 || nyf <= 0 || nxf <= 0 || !coarse || !fine) return PAT_EINVAL;
@@ -1566,6 +1587,16 @@ static int dot_into(hipStream_t st, int64_t n, const float* a, const float* b, d
   hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, a, b, n, partial);
   PAT_TRY(last_error());
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, out, 1.0);
+  return last_error();
+}
+
+int pat_absmax(int64_t n, const float* x, double* out, void* scratch, void* stream) {
+  if (n <= 0 || !x || !out || !scratch) return PAT_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* partial = static_cast<double*>(scratch);
+  hipLaunchKernelGGL(k_absmax_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, x, n, partial);
+  PAT_TRY(last_error());
+  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, out);
   return last_error();
 }
 

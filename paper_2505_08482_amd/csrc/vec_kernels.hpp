@@ -113,6 +113,62 @@ __global__ void k_project_update(int64_t n, float* __restrict__ x, const float* 
   }
 }
 
+// eq. (10)-(11): out = 0 on the active set (x on a bound with the gradient
+// pointing out of the box), else v
+__global__ void k_free_part(int64_t n, const float* __restrict__ x, const float* __restrict__ g,
+                            const float* __restrict__ lo, const float* __restrict__ hi, const float* v,
+                            float* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float xi = x[i], gi = g[i];
+    const bool active = (xi <= lo[i] && gi > 0.f) || (xi >= hi[i] && gi < 0.f);
+    out[i] = active ? 0.f : v[i];
+  }
+}
+
+// out = a x + b y (y may be null)
+__global__ void k_axpby(int64_t n, float a, const float* x, float b, const float* y, float* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+}
+
+// out = x * s (element-wise)
+__global__ void k_mul(int64_t n, const float* x, const float* __restrict__ s, float* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = x[i] * s[i];
+}
+
+// partial maxima of |x| (float64 slots of the dot-product scratch)
+__global__ __launch_bounds__(RED_THREADS) void k_absmax_partial(const float* __restrict__ x, int64_t n,
+                                                                double* __restrict__ partial) {
+  __shared__ double sh[RED_THREADS];
+  float m = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS)
+    m = fmaxf(m, fabsf(x[i]));
+  const int t = threadIdx.x;
+  sh[t] = m;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_max_partials(const double* __restrict__ partial, int nb,
+                                                              double* __restrict__ out) {
+  __shared__ double sh[RED_THREADS];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += RED_THREADS) m = fmax(m, partial[i]);
+  const int t = threadIdx.x;
+  sh[t] = m;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) *out = sh[0];
+}
+
 // Bilinear, cell-centred, same physical extent, clamped at the border.
 __device__ __forceinline__ void axis_tap(int i, int nf, int nc, int& i0, int& i1, float& t) {
   double f = (i + 0.5) * ((double)nc / (double)nf) - 0.5;

@@ -20,6 +20,7 @@ PAT_OK, PAT_EINVAL, PAT_EUNSUPPORTED, PAT_EWORKSPACE, PAT_EHIP, PAT_ENONFINITE =
 
 EXPORTS = (
     "pat_plan_create", "pat_plan_destroy", "pat_workspace_size", "pat_forward", "pat_history_field", "pat_misfit",
+    "pat_free_part", "pat_axpby", "pat_mul", "pat_absmax",
     "pat_adjoint_gradient", "pat_project_update", "pat_prolong", "pat_prolong_phys", "pat_time_interp",
     "pat_lbfgs_scratch_bytes", "pat_lbfgs_direction", "pat_lbfgs_direction_noalloc", "pat_dot", "pat_status_string",
     "pat_trace_start", "pat_trace_stop", "pat_trace_read", "pat_plan_set_tile", "pat_plan_set_col_order",
@@ -83,6 +84,10 @@ def lib() -> ctypes.CDLL:
     L.pat_lbfgs_direction.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp]
     L.pat_lbfgs_direction_noalloc.argtypes = [i64, vp, i32, vp, vp, vp, vp]
     L.pat_dot.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.pat_absmax.argtypes = [i64, vp, vp, vp, vp]
+    L.pat_free_part.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
+    L.pat_axpby.argtypes = [i64, f32, vp, f32, vp, vp, vp]
+    L.pat_mul.argtypes = [i64, vp, vp, vp, vp]
     L.pat_trace_start.argtypes = [i32]
     L.pat_trace_stop.argtypes = []
     L.pat_trace_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
@@ -293,6 +298,32 @@ def lbfgs_direction_noalloc(g, s_list: Sequence, y_list: Sequence, d):
     _check(lib().pat_lbfgs_direction_noalloc(n, _f32(g, n, "g"), npairs, ctypes.cast(S, ctypes.c_void_p),
                                              ctypes.cast(Y, ctypes.c_void_p), _f32(d, n, "d"), _stream()),
            "pat_lbfgs_direction_noalloc")
+
+
+def free_part(x, g, lo, hi, v, out):
+    """Eq. (10)-(11): ``out = 0`` on the active set of (x, g) for bounds lo, hi, else ``v``."""
+    n = x.numel()
+    _check(lib().pat_free_part(n, _f32(x, n, "x"), _f32(g, n, "g"), _f32(lo, n, "lo"), _f32(hi, n, "hi"),
+                               _f32(v, n, "v"), _f32(out, n, "out"), _stream()), "pat_free_part")
+
+
+def axpby(a: float, x, b: float, y, out):
+    """``out = a x + b y`` (``y`` None: ``out = a x``)."""
+    n = x.numel()
+    _check(lib().pat_axpby(n, float(a), _f32(x, n, "x"), float(b), _f32(y, n, "y") if y is not None else None,
+                           _f32(out, n, "out"), _stream()), "pat_axpby")
+
+
+def mul(x, s, out):
+    """``out = x * s`` element-wise."""
+    n = x.numel()
+    _check(lib().pat_mul(n, _f32(x, n, "x"), _f32(s, n, "s"), _f32(out, n, "out"), _stream()), "pat_mul")
+
+
+def absmax(x, out, scratch):
+    """``max |x|`` into the float64 device scalar ``out``."""
+    n = x.numel()
+    _check(lib().pat_absmax(n, _f32(x, n, "x"), _ptr(out), _ptr(scratch), _stream()), "pat_absmax")
 
 
 def dot(a, b, out, scratch):

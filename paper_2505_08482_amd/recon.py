@@ -15,8 +15,9 @@
 
 The optimiser works on scaled variables ``z = x / scale`` (per block: p0 and c).
 Its decisions (active set, direction safeguards, Armijo test, pair filter) are
-the ones of the float64 reference driver; the few elementwise vector updates
-between library calls (scaling, pair differences) are plain torch arithmetic.
+the ones of the float64 reference driver.  Every vector operation of an
+iteration runs in the library (``pat_free_part``, ``pat_axpby``, ``pat_mul``,
+``pat_absmax``, ``pat_dot``); the host keeps the scalars and the decisions.
 """
 from __future__ import annotations
 
@@ -75,14 +76,19 @@ class Problem:
         self.scale = torch.empty_like(lo)
         self.scale[: self.K * self.N] = 0.25
         self.scale[self.K * self.N:] = (c_hi - c_lo) / 4.0
-        self.lo_z = lo / self.scale
-        self.hi_z = hi / self.scale
+        self.inv_scale = 1.0 / self.scale
+        self.lo_z = lo * self.inv_scale
+        self.hi_z = hi * self.inv_scale
         self.mask = mask
         self.data = torch.empty(self.plan.data_shape, dtype=torch.float32, device=device)
         self.resid = torch.empty_like(self.data)
         self.J = torch.zeros(1, dtype=torch.float64, device=device)
-        self.gp0 = torch.empty(self.plan.field_shape, dtype=torch.float32, device=device)
-        self.gc = torch.empty((g.ny, g.nx), dtype=torch.float32, device=device)
+        # the physical point of the last objective call and the physical gradient,
+        # each one vector [K*N + N] whose blocks are the p0 and c fields
+        self.x = torch.empty(self.n, dtype=torch.float32, device=device)
+        self.g_all = torch.empty(self.n, dtype=torch.float32, device=device)
+        self.gp0 = self.g_all[: self.K * self.N].view(self.plan.field_shape)
+        self.gc = self.g_all[self.K * self.N:].view(g.ny, g.nx)
         self.dot_scratch = torch.empty(pat.lbfgs_scratch_bytes(0), dtype=torch.uint8, device=device)
         self.dot_out = torch.zeros(1, dtype=torch.float64, device=device)
         self.evals = 0
@@ -108,7 +114,7 @@ class Problem:
     def objective(self, z: torch.Tensor) -> float:
         """J at scaled point z (recorded forward solve + misfit, plus the prior
         terms when configured)."""
-        self.x = z * self.scale            # kept alive: the adjoint reuses these buffers
+        pat.mul(z, self.scale, self.x)     # kept: the adjoint reads the same buffers
         p0, c = self.split(self.x)
         self.plan.forward(c, p0, self.data, self.ws, ckpt_every=self.ckpt, record=True)
         self.plan.misfit(self.data, self.y, self.w, self.resid, self.J)
@@ -122,13 +128,14 @@ class Problem:
         return J
 
     def gradient(self) -> torch.Tensor:
-        """Scaled gradient at the point of the last ``objective`` call."""
+        """Scaled gradient at the point of the last ``objective`` call (a new vector)."""
         p0, c = self.split(self.x)
         self.plan.adjoint_gradient(c, p0, self.resid, self.gp0, self.gc, self.ws)
-        g = torch.cat([self.gp0.reshape(-1), self.gc.reshape(-1)])
         if self.ou is not None:
-            g = g + self.g_prior.reshape(-1)
-        return g * self.scale
+            pat.axpby(1.0, self.g_all, 1.0, self.g_prior.reshape(-1), self.g_all)
+        out = torch.empty_like(self.g_all)
+        pat.mul(self.g_all, self.scale, out)
+        return out
 
     def dot(self, a, b) -> float:
         pat.dot(a, b, self.dot_out, self.dot_scratch)
@@ -141,42 +148,68 @@ class Problem:
 
 
 def projected_lbfgs(prob: Problem, z0: torch.Tensor, iters: int, memory: int = 20, c1: float = 1e-4,
-                    max_halvings: int = 20, callback: Optional[Callable] = None):
-    """Eq. (10) iterations on scaled variables (see the module docstring)."""
-    z = z0.clone()
+                    max_halvings: int = 20, callback: Optional[Callable] = None, state: Optional[Dict] = None,
+                    log: Optional[Callable] = None):
+    """Eq. (10) iterations on scaled variables (see the module docstring).
+
+    ``state`` (optional): a dict from ``lbfgs_state`` (the iterate and the
+    stored pairs of an interrupted run) to resume from; ``z0`` is then
+    ignored.  ``log`` (optional): called after every accepted step with a dict
+    of the iteration's figures (J, projected-gradient max norm, step length,
+    trials, whether the step was quasi-Newton)."""
+    dev = z0.device
+    if state is not None:
+        z = state["z"].to(dev).clone()
+        S = [t.to(dev).clone() for t in state["S"]]
+        Y = [t.to(dev).clone() for t in state["Y"]]
+    else:
+        z = z0.clone()
+        S, Y = [], []
     pat.project_update(z, torch.zeros_like(z), 0.0, prob.lo_z, prob.hi_z)
     J = prob.objective(z)
     g = prob.gradient()
-    S: List[torch.Tensor] = []
-    Y: List[torch.Tensor] = []
-    scratch = torch.empty(pat.lbfgs_scratch_bytes(memory), dtype=torch.uint8, device=z.device)
+    scratch = torch.empty(pat.lbfgs_scratch_bytes(memory), dtype=torch.uint8, device=dev)
+    red = torch.empty(pat.lbfgs_scratch_bytes(0), dtype=torch.uint8, device=dev)
+    dmax = torch.zeros(1, dtype=torch.float64, device=dev)
     hist = [J]
     d = torch.empty_like(z)
+    gf = torch.empty_like(z)
+    step = torch.empty_like(z)
+
+    def steepest() -> bool:
+        """d = gf / max |gf| (the norm of this iteration); False if gf is zero."""
+        if gnorm == 0.0:
+            return False
+        pat.axpby(1.0 / gnorm, gf, 0.0, None, d)
+        return True
+
+    gnorm = 0.0
     it = 0
     for it in range(iters):
-        active = ((z <= prob.lo_z) & (g > 0)) | ((z >= prob.hi_z) & (g < 0))
-        gf = torch.where(active, torch.zeros_like(g), g)
+        pat.free_part(z, g, prob.lo_z, prob.hi_z, g, gf)
+        pat.absmax(gf, dmax, red)
+        gnorm = float(dmax.item())
         use_qn = bool(S)
         if use_qn:
             pat.lbfgs_direction(gf, S, Y, d, scratch)
-            d = torch.where(active, torch.zeros_like(d), d)
+            pat.free_part(z, g, prob.lo_z, prob.hi_z, d, d)
             if prob.dot(d, gf) <= 0.0:
                 S.clear(); Y.clear()
                 use_qn = False
-        if not use_qn:
-            nrm = float(gf.abs().max().item())
-            if nrm == 0.0:
-                break
-            d = gf / nrm
+        if not use_qn and not steepest():
+            break
         accepted = False
         zt = torch.empty_like(z)
+        trials = 0
         for attempt in range(2):
             alpha = 1.0
             for _ in range(max_halvings):
-                zt.copy_(z)
+                pat.axpby(1.0, z, 0.0, None, zt)
                 pat.project_update(zt, d, alpha, prob.lo_z, prob.hi_z)
                 Jt = prob.objective(zt)
-                if np.isfinite(Jt) and Jt <= J + c1 * prob.dot(g, zt - z):
+                trials += 1
+                pat.axpby(1.0, zt, -1.0, z, step)
+                if np.isfinite(Jt) and Jt <= J + c1 * prob.dot(g, step):
                     accepted = True
                     break
                 alpha *= 0.5
@@ -184,35 +217,70 @@ def projected_lbfgs(prob: Problem, z0: torch.Tensor, iters: int, memory: int = 2
                 break
             S.clear(); Y.clear()
             use_qn = False
-            d = gf / float(gf.abs().max().item())
+            if not steepest():
+                break
         if not accepted:
             break
         gt = prob.gradient()    # adjoint of the accepted trial's recorded forward solve
-        s_ = zt - z
-        y_ = gt - g
+        s_ = torch.empty_like(z)
+        y_ = torch.empty_like(z)
+        pat.axpby(1.0, zt, -1.0, z, s_)
+        pat.axpby(1.0, gt, -1.0, g, y_)
         ys = prob.dot(y_, s_)
-        if ys > 1e-10 * float(torch.linalg.vector_norm(y_).item()) * float(torch.linalg.vector_norm(s_).item()):
+        if ys > 1e-10 * np.sqrt(max(prob.dot(y_, y_), 0.0)) * np.sqrt(max(prob.dot(s_, s_), 0.0)):
             S.append(s_); Y.append(y_)
             if len(S) > memory:
                 S.pop(0); Y.pop(0)
         z, J, g = zt, Jt, gt
         hist.append(J)
+        prob.last_state = {"z": z, "S": list(S), "Y": list(Y)}
+        if log is not None:
+            log({"iter": it + 1, "J": J, "proj_grad_max": gnorm, "alpha": alpha, "trials": trials,
+                 "quasi_newton": use_qn, "pairs": len(S)})
         if callback is not None and callback(it, z, J):
             break            # the caller's stopping rule (e.g. a target error reached)
+    prob.last_state = {"z": z, "S": list(S), "Y": list(Y)}
     return z, J, hist, it + 1
+
+
+def lbfgs_state(prob) -> Dict:
+    """The iterate and the stored pairs after the last ``projected_lbfgs`` run
+    on ``prob`` (device tensors; for ``save_state`` and resuming)."""
+    return prob.last_state
 
 
 def relative_error_c(prob: Problem, z: torch.Tensor, c_true: torch.Tensor) -> float:
     """Eq. (12) for c over the reconstruction mask, in percent."""
-    _, c = prob.split(z * prob.scale)
+    x = torch.empty_like(z)
+    pat.mul(z, prob.scale, x)
+    _, c = prob.split(x)
     m = prob.mask
     return 100.0 * float(torch.linalg.vector_norm((c - c_true)[m]) / torch.linalg.vector_norm(c_true[m]))
+
+
+def save_state(path: str, level: int, iters_done: int, prob: Problem, levels_n: List[int]) -> None:
+    """Write the reconstruction's resumable state (``.npz``, no pickles): the
+    level index, the iterations done on it, the iterate (scaled, as the
+    optimiser holds it, and physical) and the stored L-BFGS pairs of the last
+    ``projected_lbfgs`` run on ``prob``."""
+    st = prob.last_state
+    x = torch.empty_like(st["z"])
+    pat.mul(st["z"], prob.scale, x)
+    S = torch.stack(st["S"]).cpu().numpy() if st["S"] else np.zeros((0, prob.n), np.float32)
+    Y = torch.stack(st["Y"]).cpu().numpy() if st["Y"] else np.zeros((0, prob.n), np.float32)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, level=np.array([level]), iters_done=np.array([iters_done]), x=x.cpu().numpy(),
+             z=st["z"].cpu().numpy(), S=S, Y=Y, levels=np.array(levels_n))
+    import os
+    os.replace(tmp, path)
 
 
 def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w: torch.Tensor, c_true_fine,
               c_lo: float = 1400.0, c_hi: float = 1600.0, iters: int = 40, memory: int = 20,
               ckpt_every: int = 0, target_Ec: Optional[float] = None, log: Optional[Callable] = None,
-              c_init: Optional[float] = None, c_fixed: float = 1500.0, prior: Optional[Dict] = None):
+              c_init: Optional[float] = None, c_fixed: float = 1500.0, prior: Optional[Dict] = None,
+              log_path: Optional[str] = None, save_path: Optional[str] = None, save_every: int = 10,
+              resume: Optional[str] = None):
     """Coarse-to-fine reconstruction (Sec. 3.1).  ``c_true_fine`` only measures
     E_c and never enters the optimisation: a tensor on the finest grid
     (resampled to coarser levels), or a callable ``level workload -> tensor``.
@@ -221,53 +289,102 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
     starting sound speed inside the mask (default: the middle of the bounds);
     ``c_fixed``: the sound speed held outside the mask.  ``prior``: the
     Ornstein-Uhlenbeck prior terms of eq. (4) (keys tau, eta_p0, sigma_p0,
-    eta_c, sigma_c, optional tol), or None for bounds only."""
+    eta_c, sigma_c, optional tol), or None for bounds only.
+
+    ``log_path``: one JSON line per iteration (level, iteration, J, max |projected
+    gradient|, step length, line-search trials, E_c, seconds).  ``save_path``:
+    the resumable state (``save_state``) every ``save_every`` iterations and at
+    the end of every level; ``resume``: such a file, to continue an interrupted
+    run (the same levels and settings) where it stopped, with the same results."""
+    import json
     device = y_fine.device
     results: List[LevelResult] = []
     z_prev = None
     prev = None
     t_all = time.perf_counter()
-    for li, wl in enumerate(levels):
-        g = wl.grid
-        y = torch.empty((wl.K, g.nt, wl.m), dtype=torch.float32, device=device)
-        pat.time_interp(y_fine, dt_fine, y, g.dt)
-        prob = Problem(wl, y, w, c_lo, c_hi, c_fixed=c_fixed, ckpt_every=ckpt_every, prior=prior)
-        if z_prev is None:
-            x0 = torch.empty(prob.n, dtype=torch.float32, device=device)
-            x0[: prob.K * prob.N] = 0.0
-            x0[prob.K * prob.N:] = 0.5 * (c_lo + c_hi) if c_init is None else c_init
-        else:
-            pg = prev.wl.grid
-            xc = (z_prev * prev.scale).view(prev.K + 1, pg.ny, pg.nx).contiguous()
-            xf = torch.empty((prob.K + 1, g.ny, g.nx), dtype=torch.float32, device=device)
-            pat.prolong_phys(xc, pg.dx, xf, g.dx)
-            x0 = xf.reshape(-1)
-            prev.close()
-        z0 = x0 / prob.scale
-        if callable(c_true_fine):
-            ct = c_true_fine(wl)
-        else:
-            ct = c_true_fine
-            if ct.shape[-1] != g.nx:
-                fg = levels[-1].grid
-                ctf = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=device)
-                pat.prolong_phys(c_true_fine.reshape(1, *c_true_fine.shape).contiguous(), fg.dx, ctf, g.dx)
-                ct = ctf[0]
-        Ec = []
-        Ts = []
-        t0 = time.perf_counter()
+    start_level, done_iters, saved = 0, 0, None
+    levels_n = [wl.grid.nx for wl in levels]
+    if resume is not None:
+        with np.load(resume, allow_pickle=False) as f:
+            saved = {k: f[k] for k in f.files}
+        if [int(v) for v in saved["levels"]] != levels_n:
+            raise ValueError("resume: the saved run used other levels")
+        start_level, done_iters = int(saved["level"][0]), int(saved["iters_done"][0])
+    logf = open(log_path, "a") if log_path else None
+    try:
+        for li, wl in enumerate(levels):
+            if li < start_level:
+                continue
+            g = wl.grid
+            y = torch.empty((wl.K, g.nt, wl.m), dtype=torch.float32, device=device)
+            pat.time_interp(y_fine, dt_fine, y, g.dt)
+            prob = Problem(wl, y, w, c_lo, c_hi, c_fixed=c_fixed, ckpt_every=ckpt_every, prior=prior)
+            state = None
+            level_iters = iters
+            if saved is not None and li == start_level:
+                x0 = torch.from_numpy(saved["x"]).to(device)
+                state = {"z": torch.from_numpy(saved["z"]).to(device),
+                         "S": [torch.from_numpy(v).to(device) for v in saved["S"]],
+                         "Y": [torch.from_numpy(v).to(device) for v in saved["Y"]]}
+                level_iters = iters - done_iters
+            elif z_prev is None:
+                x0 = torch.empty(prob.n, dtype=torch.float32, device=device)
+                x0[: prob.K * prob.N] = 0.0
+                x0[prob.K * prob.N:] = 0.5 * (c_lo + c_hi) if c_init is None else c_init
+            else:
+                pg = prev.wl.grid
+                xc = torch.empty_like(z_prev)
+                pat.mul(z_prev, prev.scale, xc)
+                xc = xc.view(prev.K + 1, pg.ny, pg.nx)
+                xf = torch.empty((prob.K + 1, g.ny, g.nx), dtype=torch.float32, device=device)
+                pat.prolong_phys(xc, pg.dx, xf, g.dx)
+                x0 = xf.reshape(-1)
+                prev.close()
+            z0 = torch.empty_like(x0)
+            pat.mul(x0, prob.inv_scale, z0)
+            if callable(c_true_fine):
+                ct = c_true_fine(wl)
+            else:
+                ct = c_true_fine
+                if ct.shape[-1] != g.nx:
+                    fg = levels[-1].grid
+                    ctf = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=device)
+                    pat.prolong_phys(c_true_fine.reshape(1, *c_true_fine.shape).contiguous(), fg.dx, ctf, g.dx)
+                    ct = ctf[0]
+            Ec = []
+            Ts = []
+            figures = {}
+            first = iters - level_iters
+            t0 = time.perf_counter()
 
-        def cb(it, z, J):
-            Ec.append(relative_error_c(prob, z, ct))
-            Ts.append(time.perf_counter() - t0)
-            if log:
-                log(f"level {g.nx}: iter {it + 1} J {J:.6e} E_c {Ec[-1]:.3f} %")
+            def cb(it, z, J):
+                Ec.append(relative_error_c(prob, z, ct))
+                Ts.append(time.perf_counter() - t0)
+                if log:
+                    log(f"level {g.nx}: iter {first + it + 1} J {J:.6e} E_c {Ec[-1]:.3f} %")
+                if logf:
+                    rec = dict(figures, level=g.nx, iter=first + it + 1, E_c=Ec[-1], t=round(Ts[-1], 4))
+                    logf.write(json.dumps(rec) + "\n")
+                    logf.flush()
+                if save_path and (first + it + 1) % save_every == 0:
+                    save_state(save_path, li, first + it + 1, prob, levels_n)
 
-        z, J, hist, nit = projected_lbfgs(prob, z0, iters, memory=memory, callback=cb)
-        torch.cuda.synchronize()
-        results.append(LevelResult(g.nx, nit, prob.evals, hist, time.perf_counter() - t0, Ec, Ts, t0 - t_all))
-        z_prev, prev = z, prob
-    x = z_prev * prev.scale
+            z, J, hist, nit = projected_lbfgs(prob, z0, level_iters, memory=memory, callback=cb, state=state,
+                                              log=figures.update)
+            torch.cuda.synchronize()
+            if save_path:
+                if li + 1 < len(levels):
+                    prob.last_state = {"z": z, "S": [], "Y": []}   # a finished level: no pairs carried
+                    save_state(save_path, li, iters, prob, levels_n)
+                else:
+                    save_state(save_path, li, first + nit, prob, levels_n)
+            results.append(LevelResult(g.nx, nit, prob.evals, hist, time.perf_counter() - t0, Ec, Ts, t0 - t_all))
+            z_prev, prev = z, prob
+    finally:
+        if logf:
+            logf.close()
+    x = torch.empty_like(z_prev)
+    pat.mul(z_prev, prev.scale, x)
     p0, c = prev.split(x)
     ct = c_true_fine(levels[-1]) if callable(c_true_fine) else c_true_fine
     out = {"levels": results, "p0": p0.clone(), "c": c.clone(), "seconds": time.perf_counter() - t_all,

@@ -39,7 +39,9 @@ def test_autograd_matches_adjoint_oracle_and_fd():
     dev = "cuda"
     plan = pat.Plan(g, wl.K, wl.sensors)
     op = WaveOperator(plan)
-    c0 = np.full_like(c_true, np.float32(1510.0))
+    # a heterogeneous iterate: midway between the true medium and 1510 m/s
+    c0 = (0.5 * (c_true.astype(np.float64) + 1510.0)).astype(np.float32)
+    assert np.ptp(c0) > 10.0
     p0 = torch.from_numpy(p0_np).to(dev).requires_grad_(True)
     c = torch.from_numpy(c0).to(dev).requires_grad_(True)
     y = torch.from_numpy(y_np).to(dev)
@@ -167,3 +169,51 @@ def test_reconstruction_decreases_J_and_runs_multigrid():
         print(f"[multigrid] level {lv.n}: iters {lv.iters} J {lv.J[0]:.4e} -> {lv.J[-1]:.4e} E_c {lv.E_c}")
         assert lv.J[-1] <= lv.J[0]
     assert np.isfinite(out["E_c"])
+
+
+def test_resume_gives_the_uninterrupted_result(tmp_path):
+    """A two-level reconstruction stopped in the middle of its first level and
+    resumed from the saved state (iterate and L-BFGS pairs), and one stopped
+    after its first level, both end with exactly the iterate of the
+    uninterrupted run; the JSON-lines log holds one record per iteration."""
+    import json
+    import torch
+    from paper_2505_08482_amd import recon
+
+    def level(n, nt, pml):
+        dx = 12.8e-3 / n
+        g = I.Grid(nx=n, ny=n, dx=dx, dt=I.cfl_dt(dx), nt=nt, pml=pml)
+        rs = 5.0e-3 / dx
+        return I.Workload(f"mg_{n}", g, K=2, m=48, sensor_radius_px=rs, support_radius_px=rs - 4.0 * n / 128)
+    fine, coarse = level(128, 161, 10), level(64, 81, 6)
+    c_t, p_t = I.phantoms(fine, 2, case=5)
+    clean, _ = kspace.forward(fine.grid, fine.sensors, c_t, p_t, record=False)
+    y, sigma = I.add_noise(clean, seed=78)
+    args = (torch.from_numpy(y.astype(np.float32)).cuda(), fine.grid.dt,
+            torch.from_numpy((1.0 / sigma).astype(np.float32)).cuda(), torch.from_numpy(c_t.astype(np.float32)).cuda())
+    announce("multigrid uninterrupted, 6 + 6 iterations")
+    log = tmp_path / "log.jsonl"
+    ref = recon.multigrid([coarse, fine], *args, iters=6, log_path=str(log))
+    recs = [json.loads(line) for line in open(log)]
+    assert len(recs) == sum(lv.iters for lv in ref["levels"])
+    assert {"level", "iter", "J", "proj_grad_max", "alpha", "trials", "E_c", "t"} <= set(recs[0])
+    st = tmp_path / "state.npz"
+    announce("multigrid stopped after 3 iterations of the first level, resumed")
+    # an interrupted run: the first level alone for 3 of its 6 iterations, saving its state
+    recon.multigrid([coarse], *args, iters=3, save_path=str(st), save_every=3)
+    with np.load(st, allow_pickle=False) as f:
+        saved = {k: f[k] for k in f.files}
+    # the same state as a file of the two-level run
+    np.savez(st, level=saved["level"], iters_done=saved["iters_done"], x=saved["x"], z=saved["z"], S=saved["S"],
+             Y=saved["Y"], levels=np.array([coarse.grid.nx, fine.grid.nx]))
+    res = recon.multigrid([coarse, fine], *args, iters=6, resume=str(st))
+    assert torch.equal(res["c"], ref["c"]) and torch.equal(res["p0"], ref["p0"])
+    announce("multigrid stopped after the first level, resumed")
+    st2 = tmp_path / "state2.npz"
+    recon.multigrid([coarse], *args, iters=6, save_path=str(st2), save_every=100)
+    with np.load(st2, allow_pickle=False) as f:
+        saved = {k: f[k] for k in f.files}
+    np.savez(st2, level=saved["level"], iters_done=saved["iters_done"], x=saved["x"], z=saved["z"], S=saved["S"],
+             Y=saved["Y"], levels=np.array([coarse.grid.nx, fine.grid.nx]))
+    res2 = recon.multigrid([coarse, fine], *args, iters=6, resume=str(st2))
+    assert torch.equal(res2["c"], ref["c"]) and torch.equal(res2["p0"], ref["p0"])

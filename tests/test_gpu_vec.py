@@ -120,3 +120,39 @@ def test_lbfgs_direction_and_dot(torch, npairs):
     out = torch.zeros(1, dtype=torch.float64, device="cuda")
     pat.dot(T(g), T(g), out, scratch)
     assert abs(out.item() - float(np.dot(g.astype(np.float64), g.astype(np.float64)))) < 1e-9 * out.item()
+
+
+def test_optimiser_vector_ops(torch):
+    """The vector operations of a projected L-BFGS iteration: the free part of
+    a vector for the active set of eq. (10)-(11) (exact selection, as the
+    oracle driver forms it), a x + b y and x * s (float32 rounding of one
+    operation), max |x| (exact)."""
+    from paper_2505_08482_amd import pat
+    rng = np.random.default_rng(17)
+    n = 100_003
+    lo = rng.uniform(-1, 0, n).astype(np.float32)
+    hi = (lo + rng.uniform(0.5, 1.5, n)).astype(np.float32)
+    x = rng.uniform(-1.5, 1.5, n).astype(np.float32)
+    x = np.clip(x, lo, hi)                       # points on and inside the bounds
+    g = rng.standard_normal(n).astype(np.float32)
+    v = rng.standard_normal(n).astype(np.float32)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    announce("optimiser vector ops")
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    pat.free_part(T(x), T(g), T(lo), T(hi), T(v), out)
+    active = ((x <= lo) & (g > 0)) | ((x >= hi) & (g < 0))
+    assert active.sum() > 1000 and (~active).sum() > 1000
+    assert np.array_equal(out.cpu().numpy(), np.where(active, 0.0, v).astype(np.float32))
+    vv = T(v.copy())
+    pat.free_part(T(x), T(g), T(lo), T(hi), vv, vv)          # in place
+    assert np.array_equal(vv.cpu().numpy(), out.cpu().numpy())
+    pat.axpby(0.75, T(x), -2.5, T(g), out)
+    ref = (np.float32(0.75) * x + np.float32(-2.5) * g).astype(np.float32)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 2e-6 * np.max(np.abs(ref))
+    pat.axpby(3.0, T(x), 0.0, None, out)
+    assert np.array_equal(out.cpu().numpy(), np.float32(3.0) * x)
+    pat.mul(T(x), T(g), out)
+    assert np.array_equal(out.cpu().numpy(), x * g)
+    m = torch.zeros(1, dtype=torch.float64, device="cuda")
+    pat.absmax(T(g), m, torch.empty(pat.lbfgs_scratch_bytes(0), dtype=torch.uint8, device="cuda"))
+    assert float(m.item()) == float(np.max(np.abs(g)))
