@@ -384,6 +384,58 @@ def time_to_solution(wl_fine, c_true, y_fine, w, iters: int, target: float = 2.0
                         "E_c_last": round(lv.E_c[-1], 3) if lv.E_c else None} for lv in out["levels"]]}
 
 
+def time_to_solution_finer_data(K: int, iters: int, target: float = 2.0):
+    """The same multigrid reconstruction with data simulated on the finer 768^2
+    grid (inputs.data_grid_768: no inverse crime), phantoms of the throughput
+    workload's generators drawn on that grid (seeds 3000-3008, noise 3500);
+    E_c against the true sound speed interpolated to each level."""
+    import torch
+    from paper_2505_08482_amd import pat
+    dw = I.data_grid_768(K=K)
+    c_np, p0_np = I.data_grid_phantoms(dw, 3)
+    plan = pat.Plan(dw.grid, K, dw.sensors)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    data = torch.empty(plan.data_shape, dtype=torch.float32, device="cuda")
+    ws = plan.workspace(0)
+    t0 = time.perf_counter()
+    plan.forward(T(c_np), T(p0_np), data, ws, record=False)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    del ws
+    plan.close()
+    y_np, sigma = I.add_noise(data.cpu().numpy().astype(np.float64), seed=3500)
+    y = T(y_np)
+    w = T(1.0 / sigma)
+    c_data = T(c_np).reshape(1, dw.grid.ny, dw.grid.nx)
+
+    def truth(level):
+        out = torch.empty((1, level.grid.ny, level.grid.nx), dtype=torch.float32, device="cuda")
+        pat.prolong_phys(c_data, dw.grid.dx, out, level.grid.dx)
+        return out[0]
+
+    from paper_2505_08482_amd import recon
+    levels = [I.config3_level(n, K=K) for n in (128, 256, 512)]
+    t0 = time.perf_counter()
+    out = recon.multigrid(levels, y, dw.grid.dt, w, truth, iters=iters)
+    total = time.perf_counter() - t0
+    res = {"data_grid": dw.grid.nx, "data_nt": dw.grid.nt, "data_seconds": round(t_data, 2),
+           "data_rate_grid_pt_steps_per_s": round(K * dw.grid.nx * dw.grid.ny * dw.grid.nt / t_data, 1),
+           "target_E_c_percent": target, "final_E_c_percent": round(out["E_c"], 3),
+           "total_seconds": round(total, 2), "reached": None,
+           "levels": [{"n": lv.n, "iters": lv.iters, "evals": lv.evals, "seconds": round(lv.seconds, 2),
+                       "E_c_first": round(lv.E_c[0], 3) if lv.E_c else None,
+                       "E_c_last": round(lv.E_c[-1], 3) if lv.E_c else None} for lv in out["levels"]]}
+    its = 0
+    for lv in out["levels"]:
+        hit = next((i for i, e in enumerate(lv.E_c) if e <= target), None)
+        if hit is not None and lv.n == 512:
+            res["reached"] = {"level": lv.n, "iteration_at_level": hit + 1, "iterations_total": its + hit + 1,
+                              "seconds": round(lv.t_start + lv.t[hit], 2)}
+            break
+        its += lv.iters
+    return res
+
+
 def network_timing():
     """The learned start's network at the fine-level size (512^2, batch 4):
     forward and training-step times, convolution flop rates, and the forward
@@ -392,19 +444,20 @@ def network_timing():
     return learned.time_network(4, 5)
 
 
-def learned_start(cases, fine_iters: int = 20, targets=(2.0, 1.0)):
+def learned_start(cases, fine_iters: int = 20, targets=(2.0, 1.0), data_grid: int = 512):
     """Held-out phantoms (the 256^2 workload's generators at 512^2, K = 8,
     seeds 5000 + case): plain multigrid 128 -> 256 -> 512 against the coarse
     level followed by the fine level started from the trained network's
     proposal (and, for the gain of the network alone, from the plain
     interpolation of the same coarse iterate).  Iterations and wall time from
-    the start of each run to E_c <= each target on the finest grid."""
+    the start of each run to E_c <= each target on the finest grid.
+    ``data_grid = 768``: the phantoms and data on the finer 768^2 grid."""
     import os as _os
     from paper_2505_08482_amd import learned
     if not _os.path.exists(learned.DEFAULT_WEIGHTS):
         return {"error": "no trained weights in the package"}
     net = learned.load_weights(learned.DEFAULT_WEIGHTS)
-    rows = [learned.evaluate_case(net, c, fine_iters=fine_iters, targets=targets,
+    rows = [learned.evaluate_case(net, c, fine_iters=fine_iters, targets=targets, data_grid=data_grid,
                                   log=lambda m: progress("learned_start " + m)) for c in cases]
     summary = {}
     for run in ("plain_multigrid", "interpolated", "learned"):
@@ -418,7 +471,7 @@ def learned_start(cases, fine_iters: int = 20, targets=(2.0, 1.0)):
     for r in rows:            # keep the JSON line short: trajectories stay in the rows' summaries
         for run in ("plain_multigrid", "interpolated", "learned"):
             r[run].pop("t", None)
-    return {"targets_E_c_percent": list(targets), "cases": list(cases), "summary": summary,
+    return {"data_grid": data_grid, "targets_E_c_percent": list(targets), "cases": list(cases), "summary": summary,
             "mean_E_c_fine_start": {k: round(float(np.mean([r[k]["E_c_start"] for r in rows])), 3)
                                     for k in ("interpolated", "learned")},
             "rows": rows}
@@ -574,9 +627,13 @@ def main() -> int:
                          ("checkpointed", lambda: checkpointed(plan, wl, c, t_p0, y, w, evaluation_ms=ms)),
                          ("batch", lambda: batch_w3(args.batch_evals)),
                          ("time_to_solution", lambda: time_to_solution(wl, t_c_true, y, w, args.tts_iters)),
+                         ("time_to_solution_finer_data", lambda: time_to_solution_finer_data(wl.K, args.tts_iters)),
                          ("paper_geometry", lambda: paper_geometry(args.tts_iters)),
                          ("network", network_timing),
                          ("learned_start", lambda: learned_start(range(args.learned_cases))
+                          if args.learned_cases > 0 else {"skipped": True}),
+                         ("learned_start_finer_data", lambda: learned_start(range(args.learned_cases),
+                                                                            data_grid=768)
                           if args.learned_cases > 0 else {"skipped": True})):
             progress(f"{name} ...")
             try:

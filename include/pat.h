@@ -74,7 +74,7 @@ typedef struct pat_plan pat_plan;
  * centre).  Sec. 2.2: the pressure at a sensor is the bilinear interpolation
  * of its four surrounding pixels; the adjoint injects with the transpose.
  * Supported axis lengths: 32 36 40 48 64 81 84 96 125 128 160 175 192 243 256
- * 375 384 512 (products of 2, 3, 5, 7 with a compiled radix plan).
+ * 375 384 512 768 (products of 2, 3, 5, 7 with a compiled radix plan).
  * Errors: PAT_EINVAL (sizes, sensor outside the interpolation range),
  * PAT_EUNSUPPORTED (axis length, K > 64), PAT_EHIP (table upload).
  * The plan owns small device tables (twiddles, PML profiles, sensor taps,

@@ -13,7 +13,7 @@ namespace {
 // non-square grids, and power-of-two grids run with that family)
 #define PAT_BATCH_GENERIC(X)                                                                              \
   X(32) X(36) X(40) X(48) X(64) X(81) X(84) X(96) X(125) X(128) X(160) X(175) X(192) X(243) X(256) X(375) \
-  X(384) X(512)
+  X(384) X(512) X(768)
 
 int launched() { return hipGetLastError() == hipSuccess ? 0 : -4; }
 

@@ -173,6 +173,7 @@ template <> struct Plan<256> { using L = RList<8, 8, 4>; };
 template <> struct Plan<375> { using L = RList<5, 5, 5, 3>; };
 template <> struct Plan<384> { using L = RList<8, 8, 3, 2>; };
 template <> struct Plan<512> { using L = RList<8, 8, 8>; };
+template <> struct Plan<768> { using L = RList<8, 8, 4, 3>; };
 
 // Threads per transform: a power of two near N/8, between 8 and 64.
 template <int N> struct Threads {

@@ -25,7 +25,7 @@ using namespace pat;
 
 namespace {
 
-constexpr int kSupported[] = {32, 36, 40, 48, 64, 81, 84, 96, 125, 128, 160, 175, 192, 243, 256, 375, 384, 512};
+constexpr int kSupported[] = {32, 36, 40, 48, 64, 81, 84, 96, 125, 128, 160, 175, 192, 243, 256, 375, 384, 512, 768};
 
 bool supported(int n) {
   for (int s : kSupported)
@@ -35,7 +35,7 @@ bool supported(int n) {
 
 #define PAT_SIZE_CASES(X)                                                                                  \
   X(32) X(36) X(40) X(48) X(64) X(81) X(84) X(96) X(125) X(128) X(160) X(175) X(192) X(243) X(256) X(375) \
-  X(384) X(512)
+  X(384) X(512) X(768)
 
 #define PAT_FAST_CASES(X) X(32) X(64) X(128) X(256) X(512)
 

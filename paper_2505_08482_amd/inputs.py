@@ -144,6 +144,40 @@ def w1(K: int = 8, nt: int = 4000) -> Workload:
     return wl
 
 
+def data_grid_768(K: int = 8) -> Workload:
+    """A data grid finer than the finest reconstruction level (Sec. 4.1.2
+    simulates the data on a grid other than the reconstruction grid): 768^2
+    over the same 51.2 mm square (0.0667 mm), a 2 mm PML (30 points), the 512
+    sensors at the same physical radius (19.5 mm), and 6000 samples at 12.5 ns
+    (the same 75 us as the 512^2 level's 4000 at 18.75 ns)."""
+    n = 768
+    dx = 51.2e-3 / n
+    dt = cfl_dt(dx)
+    nt = int(round(4000 * cfl_dt(1e-4) / dt))
+    g = Grid(nx=n, ny=n, dx=dx, dt=dt, nt=nt, pml=30)
+    rs = sensor_radius_px(512) * 1e-4 / dx
+    return Workload(f"data768_K{K}_nt{nt}", g, K=K, m=512, sensor_radius_px=rs, support_radius_px=rs - 6.0)
+
+
+def data_grid_phantoms(wl: Workload, config: int, case: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """The generators of ``phantoms`` drawn directly on a finer data grid, with
+    the lengths in pixels scaled by the grid's refinement over 512 (the same
+    physical correlation length, blob width and vessel width).  Seeds as in
+    ``phantoms``."""
+    n = wl.grid.nx
+    f = n / 512.0
+    base = 1000 * config + case
+    c = grf_c(n, np.random.default_rng(base), wl.support_radius_px, corr_px=40.0 * f)
+    p0 = np.zeros((wl.K, n, n))
+    for k in range(wl.K):
+        rng = np.random.default_rng(base + k + 1)
+        if config in (2, 4, 5):
+            p0[k] = vessel_p0(n, rng, wl.support_radius_px, half_width_px=1.0 * f)
+        else:
+            p0[k] = blob_p0(n, rng, wl.sensor_radius_px - 6.0 * f, sigma_px=2.0 * f)
+    return c, p0
+
+
 # ---------------------------------------------------------------------------
 # The paper's own geometry (Sec. 4, Table 1)
 # ---------------------------------------------------------------------------

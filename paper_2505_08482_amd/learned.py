@@ -329,8 +329,12 @@ def coarse_level(y_fine: torch.Tensor, dt_fine: float, w: torch.Tensor, K: int, 
     try:
         x0 = torch.zeros(prob.n, dtype=torch.float32, device="cuda")
         x0[prob.K * prob.N:] = 0.5 * (c_lo + c_hi)
-        z, J, hist, nit = recon.projected_lbfgs(prob, x0 / prob.scale, iters)
-        p0, c = prob.split(z * prob.scale)
+        z0 = torch.empty_like(x0)
+        pat.mul(x0, prob.inv_scale, z0)
+        z, J, hist, nit = recon.projected_lbfgs(prob, z0, iters)
+        x = torch.empty_like(z)
+        pat.mul(z, prob.scale, x)
+        p0, c = prob.split(x)
         out = CoarseResult(c.clone(), p0.clone(), prob.gp0.clone(), nit, 0.0, g.dx)
         torch.cuda.synchronize()
         out.seconds = time.perf_counter() - t0
@@ -472,14 +476,21 @@ def fine_level(fine: I.Workload, y_fine: torch.Tensor, w: torch.Tensor, c0: torc
     prob = recon.Problem(fine, y_fine, w, c_lo, c_hi)
     try:
         x0 = torch.cat([p00.reshape(-1), c0.reshape(-1)]).contiguous()
-        z0 = x0 / prob.scale
+        z0 = torch.empty_like(x0)
+        pat.mul(x0, prob.inv_scale, z0)
         pat.project_update(z0, torch.zeros_like(z0), 0.0, prob.lo_z, prob.hi_z)
         mask = prob.mask
-        E = [relative_error(prob.split(z0 * prob.scale)[1], c_true, mask)]
+        xs = torch.empty_like(z0)
+
+        def c_of(z):
+            pat.mul(z, prob.scale, xs)
+            return prob.split(xs)[1]
+
+        E = [relative_error(c_of(z0), c_true, mask)]
         T = [time.perf_counter() - t_origin]
 
         def cb(it, z, J):
-            E.append(relative_error(prob.split(z * prob.scale)[1], c_true, mask))
+            E.append(relative_error(c_of(z), c_true, mask))
             T.append(time.perf_counter() - t_origin)
             return target is not None and E[-1] <= target
 
@@ -508,20 +519,43 @@ def _hits(E: Sequence[float], T: Sequence[float], targets: Sequence[float], its_
 
 
 def evaluate_case(net: Optional[UNet], case: int, K: int = 8, coarse_iters: int = 40, fine_iters: int = 20,
-                  targets: Sequence[float] = (2.0, 1.0), plain_multigrid: bool = True, log=None) -> Dict:
+                  targets: Sequence[float] = (2.0, 1.0), plain_multigrid: bool = True, log=None,
+                  data_grid: int = FINE_N) -> Dict:
     """One held-out phantom (the 256^2 workload's generators at 512^2, seeds
     5000 + case): plain multigrid 128 -> 256 -> 512 against the coarse level
     followed directly by the fine level, started from the plain interpolation
     of the coarse iterate and from the network's proposal.  For each start:
     E_c at the fine start and after every fine iteration, and the iterations
     and wall time (from the start of the run) at which E_c first falls to each
-    target; the fine level stops at the smallest target."""
+    target; the fine level stops at the smallest target.
+
+    ``data_grid = 768``: the phantom and its data on the finer 768^2 grid
+    (``inputs.data_grid_768``) instead of the finest reconstruction grid, and
+    E_c measured against the true sound speed interpolated to each level."""
     from . import recon
     fine = I.config3_level(FINE_N, K=K)
-    c_np, p0_np = I.phantoms(fine, 5, case=case)
-    c_true = torch.from_numpy(c_np.astype(np.float32)).cuda()
-    y, w = simulate(fine, c_np, p0_np, noise_seed=5000 + case + 500)
-    dt = fine.grid.dt
+    if data_grid == FINE_N:
+        c_np, p0_np = I.phantoms(fine, 5, case=case)
+        c_true = torch.from_numpy(c_np.astype(np.float32)).cuda()
+        y, w = simulate(fine, c_np, p0_np, noise_seed=5000 + case + 500)
+        dt = fine.grid.dt
+        truth = c_true
+    else:
+        dw = I.data_grid_768(K=K)
+        c_np, p0_np = I.data_grid_phantoms(dw, 5, case=case)
+        y, w = simulate(dw, c_np, p0_np, noise_seed=5000 + case + 500)
+        dt = dw.grid.dt
+        c_data = torch.from_numpy(c_np.astype(np.float32)).cuda().reshape(1, dw.grid.ny, dw.grid.nx)
+
+        def truth(level):
+            out = torch.empty((1, level.grid.ny, level.grid.nx), dtype=torch.float32, device="cuda")
+            pat.prolong_phys(c_data, dw.grid.dx, out, level.grid.dx)
+            return out[0]
+        c_true = truth(fine)
+    y_fine = y
+    if data_grid != FINE_N:   # the fine level's own time grid
+        y_fine = torch.empty((K, fine.grid.nt, fine.m), dtype=torch.float32, device="cuda")
+        pat.time_interp(y, dt, y_fine, fine.grid.dt)
     res: Dict = {"case": case}
     stop = min(targets) if targets else None
     # coarse level, shared by both starts
@@ -544,7 +578,7 @@ def evaluate_case(net: Optional[UNet], case: int, K: int = 8, coarse_iters: int 
         starts["learned"] = (c_net, time.perf_counter() - t1)
     for name, (c0, extra) in starts.items():
         t_origin = time.perf_counter() - (t_coarse + extra)
-        E, T = fine_level(fine, y, w, c0, p0_up, c_true, fine_iters, target=stop, t_origin=t_origin)
+        E, T = fine_level(fine, y_fine, w, c0, p0_up, c_true, fine_iters, target=stop, t_origin=t_origin)
         res[name] = {"E_c_start": round(E[0], 3), "E_c_last": round(E[-1], 3), "fine_iterations": len(E) - 1,
                      "E_c": [round(e, 3) for e in E], "t": [round(t, 2) for t in T],
                      "to_target": _hits(E, T, targets, co.iters, 0)}
@@ -555,7 +589,7 @@ def evaluate_case(net: Optional[UNet], case: int, K: int = 8, coarse_iters: int 
         levels = [I.config3_level(n, K=K) for n in (COARSE_N, 256, FINE_N)]
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out = recon.multigrid(levels, y, dt, w, c_true, iters=coarse_iters)
+        out = recon.multigrid(levels, y, dt, w, truth, iters=coarse_iters)
         total = time.perf_counter() - t2
         fl = out["levels"][-1]
         its_before = sum(lv.iters for lv in out["levels"][:-1])
@@ -572,22 +606,68 @@ def evaluate_case(net: Optional[UNet], case: int, K: int = 8, coarse_iters: int 
 # ---------------------------------------------------------------------------
 # Command line: generate pairs, train, evaluate
 # ---------------------------------------------------------------------------
-def generate_pairs(start: int, count: int, K: int = 8, coarse_iters: int = 40, log=print) -> Dict[str, np.ndarray]:
+def _dataset_sum(g_p0: torch.Tensor) -> torch.Tensor:
+    """Sum over the datasets of the p0 gradients (in dataset order)."""
+    out = g_p0[0].clone()
+    for k in range(1, g_p0.shape[0]):
+        pat.axpby(1.0, out, 1.0, g_p0[k], out)
+    return out
+
+
+def generate_pairs(start: int, count: int, K: int = 8, coarse_iters: int = 40, log=print,
+                   batch: int = 1) -> Dict[str, np.ndarray]:
+    """Training pairs ``start .. start + count - 1``: each phantom's data on the
+    fine grid, the 40-iteration coarse level of plain multigrid, its sound
+    speed and summed p0 gradient.  ``batch`` > 1 runs that many coarse
+    reconstructions in lockstep (``recon.batched_projected_lbfgs``: shared
+    launches), with the same results as one at a time."""
+    from . import recon
     fine = I.config3_level(FINE_N, K=K)
+    coarse = I.config3_level(COARSE_N, K=K)
+    m = torch.from_numpy(fine.mask().astype(np.bool_)).cuda()
     cs, gs, ecs, secs = [], [], [], []
-    for j in range(start, start + count):
+    for g0 in range(start, start + count, batch):
+        group = list(range(g0, min(g0 + batch, start + count)))
         t0 = time.perf_counter()
-        c_np, p0_np = pair_phantoms(fine, j)
-        y, w = simulate(fine, c_np, p0_np, noise_seed=[5, 1, j, 500])
-        co = coarse_level(y, fine.grid.dt, w, K, iters=coarse_iters)
-        cs.append(co.c.cpu().numpy())
-        gs.append(co.g_p0.sum(0).cpu().numpy())
-        c_up, _ = fine_inputs(co, fine)
-        m = torch.from_numpy(fine.mask().astype(np.bool_)).cuda()
-        ecs.append(relative_error(c_up, torch.from_numpy(c_np.astype(np.float32)).cuda(), m))
-        secs.append(time.perf_counter() - t0)
-        if log:
-            log(f"pair {j}: coarse iterations {co.iters}, interpolated E_c {ecs[-1]:.3f} %, {secs[-1]:.2f} s")
+        truths, probs, z0s = [], [], []
+        for j in group:
+            c_np, p0_np = pair_phantoms(fine, j)
+            y, w = simulate(fine, c_np, p0_np, noise_seed=[5, 1, j, 500])
+            truths.append(c_np)
+            if batch == 1:
+                co = coarse_level(y, fine.grid.dt, w, K, iters=coarse_iters)
+                results = [(co.c, co.g_p0, co.iters, co.dx)]
+                break
+            g = coarse.grid
+            yc = torch.empty((K, g.nt, coarse.m), dtype=torch.float32, device="cuda")
+            pat.time_interp(y, fine.grid.dt, yc, g.dt)
+            del y
+            prob = recon.Problem(coarse, yc, w, 1400.0, 1600.0)
+            x0 = torch.zeros(prob.n, dtype=torch.float32, device="cuda")
+            x0[prob.K * prob.N:] = 1500.0
+            z0 = torch.empty_like(x0)
+            pat.mul(x0, prob.inv_scale, z0)
+            probs.append(prob)
+            z0s.append(z0)
+        if batch > 1:
+            out = recon.batched_projected_lbfgs(probs, z0s, coarse_iters)
+            results = []
+            for prob, (z, J, hist, nit) in zip(probs, out):
+                x = torch.empty_like(z)
+                pat.mul(z, prob.scale, x)
+                results.append((prob.split(x)[1].clone(), prob.gp0.clone(), nit, coarse.grid.dx))
+                prob.close()
+        torch.cuda.synchronize()
+        dt_each = (time.perf_counter() - t0) / len(group)
+        for j, c_np, (c, gp0, nit, dx) in zip(group, truths, results):
+            cs.append(c.cpu().numpy())
+            gs.append(_dataset_sum(gp0).cpu().numpy())
+            co = CoarseResult(c, gp0, gp0, nit, 0.0, dx)
+            c_up, _ = fine_inputs(co, fine)
+            ecs.append(relative_error(c_up, torch.from_numpy(c_np.astype(np.float32)).cuda(), m))
+            secs.append(dt_each)
+            if log:
+                log(f"pair {j}: coarse iterations {nit}, interpolated E_c {ecs[-1]:.3f} %, {dt_each:.2f} s")
     return {"index": np.arange(start, start + count), "c": np.stack(cs).astype(np.float32),
             "gsum": np.stack(gs).astype(np.float32), "E_c_interp": np.array(ecs), "seconds": np.array(secs)}
 
@@ -676,6 +756,7 @@ def main(argv=None) -> int:
     g.add_argument("--start", type=int, default=0)
     g.add_argument("--count", type=int, default=8)
     g.add_argument("--out", required=True)
+    g.add_argument("--batch", type=int, default=1, help="coarse reconstructions run in lockstep")
     t = sub.add_parser("train", help="train the network on generated pairs")
     t.add_argument("--pairs", nargs="+", required=True)
     t.add_argument("--epochs", type=int, default=10)
@@ -692,11 +773,13 @@ def main(argv=None) -> int:
     e.add_argument("--cases", type=int, nargs="+", default=[0, 1])
     e.add_argument("--fine-iters", type=int, default=20)
     e.add_argument("--no-multigrid", action="store_true")
+    e.add_argument("--data-grid", type=int, default=FINE_N, choices=(FINE_N, 768),
+                   help="grid the phantom's data are simulated on (768: finer than the reconstruction grid)")
     e.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     if a.cmd == "gen":
-        d = generate_pairs(a.start, a.count, log=log)
+        d = generate_pairs(a.start, a.count, log=log, batch=a.batch)
         np.savez(a.out, **d)
         return 0
     if a.cmd == "train":
@@ -734,8 +817,8 @@ def main(argv=None) -> int:
         return 0
     if a.cmd == "eval":
         net = load_weights(a.weights) if a.weights else None
-        rows = [evaluate_case(net, c, fine_iters=a.fine_iters, plain_multigrid=not a.no_multigrid, log=log)
-                for c in a.cases]
+        rows = [evaluate_case(net, c, fine_iters=a.fine_iters, plain_multigrid=not a.no_multigrid, log=log,
+                              data_grid=a.data_grid) for c in a.cases]
         if a.out:
             with open(a.out, "w") as f:
                 json.dump(rows, f, indent=1)

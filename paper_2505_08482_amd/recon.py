@@ -243,6 +243,151 @@ def projected_lbfgs(prob: Problem, z0: torch.Tensor, iters: int, memory: int = 2
     return z, J, hist, it + 1
 
 
+class _Lane:
+    """State of one problem in the lockstep driver (the same decisions, in the
+    same order, as ``projected_lbfgs``)."""
+
+    def __init__(self, prob: Problem, z0: torch.Tensor, iters: int, memory: int):
+        self.prob, self.iters, self.memory = prob, iters, memory
+        self.z = z0.clone()
+        pat.project_update(self.z, torch.zeros_like(self.z), 0.0, prob.lo_z, prob.hi_z)
+        self.zt = self.z            # the point to evaluate next
+        self.S, self.Y = [], []
+        self.J = None
+        self.g = None
+        self.hist = []
+        self.it = 0
+        self.done = False
+        self.d = torch.empty_like(self.z)
+        self.gf = torch.empty_like(self.z)
+        self.step = torch.empty_like(self.z)
+        self.red = torch.empty(pat.lbfgs_scratch_bytes(0), dtype=torch.uint8, device=z0.device)
+        self.dmax = torch.zeros(1, dtype=torch.float64, device=z0.device)
+        self.scratch = torch.empty(pat.lbfgs_scratch_bytes(memory), dtype=torch.uint8, device=z0.device)
+
+    def job(self) -> Dict:
+        p = self.prob
+        p0, c = p.split(p.x)
+        return {"plan": p.plan, "c": c, "p0": p0, "y": p.y, "w": p.w, "data": p.data, "resid": p.resid,
+                "J": p.J, "g_p0": p.gp0, "g_c": p.gc, "ws": p.ws}
+
+    def load(self):
+        pat.mul(self.zt, self.prob.scale, self.prob.x)
+
+    def _start_iteration(self):
+        """Direction and the first trial of iteration self.it (True), or stop (False)."""
+        p = self.prob
+        pat.free_part(self.z, self.g, p.lo_z, p.hi_z, self.g, self.gf)
+        pat.absmax(self.gf, self.dmax, self.red)
+        self.gnorm = float(self.dmax.item())
+        self.use_qn = bool(self.S)
+        if self.use_qn:
+            pat.lbfgs_direction(self.gf, self.S, self.Y, self.d, self.scratch)
+            pat.free_part(self.z, self.g, p.lo_z, p.hi_z, self.d, self.d)
+            if p.dot(self.d, self.gf) <= 0.0:
+                self.S.clear(); self.Y.clear()
+                self.use_qn = False
+        if not self.use_qn and not self._steepest():
+            return False
+        self.attempt, self.alpha, self.halvings = 0, 1.0, 0
+        self._propose()
+        return True
+
+    def _steepest(self) -> bool:
+        if self.gnorm == 0.0:
+            return False
+        pat.axpby(1.0 / self.gnorm, self.gf, 0.0, None, self.d)
+        return True
+
+    def _propose(self):
+        self.zt = torch.empty_like(self.z)
+        pat.axpby(1.0, self.z, 0.0, None, self.zt)
+        pat.project_update(self.zt, self.d, self.alpha, self.prob.lo_z, self.prob.hi_z)
+
+    def evaluated(self, c1: float, max_halvings: int):
+        """Take the objective and gradient just computed at self.zt."""
+        p = self.prob
+        p.evals += 1
+        Jt = float(p.J.item())
+        gt = torch.empty_like(p.g_all)
+        pat.mul(p.g_all, p.scale, gt)
+        if self.J is None:                       # the starting point
+            self.J, self.g = Jt, gt
+            self.hist.append(Jt)
+            if self.iters <= 0 or not self._start_iteration():
+                self.done = True
+            return
+        pat.axpby(1.0, self.zt, -1.0, self.z, self.step)
+        if np.isfinite(Jt) and Jt <= self.J + c1 * p.dot(self.g, self.step):
+            s_ = torch.empty_like(self.z)
+            y_ = torch.empty_like(self.z)
+            pat.axpby(1.0, self.zt, -1.0, self.z, s_)
+            pat.axpby(1.0, gt, -1.0, self.g, y_)
+            ys = p.dot(y_, s_)
+            if ys > 1e-10 * np.sqrt(max(p.dot(y_, y_), 0.0)) * np.sqrt(max(p.dot(s_, s_), 0.0)):
+                self.S.append(s_); self.Y.append(y_)
+                if len(self.S) > self.memory:
+                    self.S.pop(0); self.Y.pop(0)
+            self.z, self.J, self.g = self.zt, Jt, gt
+            self.hist.append(Jt)
+            self.it += 1
+            if self.it >= self.iters or not self._start_iteration():
+                self.done = True
+            return
+        self.alpha *= 0.5
+        self.halvings += 1
+        if self.halvings < max_halvings:
+            self._propose()
+            return
+        if self.use_qn and self.attempt == 0:    # restart with steepest descent
+            self.S.clear(); self.Y.clear()
+            self.use_qn = False
+            self.attempt, self.alpha, self.halvings = 1, 1.0, 0
+            if self._steepest():
+                self._propose()
+                return
+        self.done = True                         # no acceptable step
+
+
+def batched_projected_lbfgs(probs: List[Problem], z0s: List[torch.Tensor], iters: int, memory: int = 20,
+                            c1: float = 1e-4, max_halvings: int = 20, nstreams: int = 4):
+    """``projected_lbfgs`` on many independent problems in lockstep: every
+    round evaluates one point of every problem (its next line-search trial, or
+    its last point again once it has finished) with one ``pat_batch_gradient``
+    call, so problems of one grid size share every launch.  Each problem takes
+    exactly the iterates it takes alone (an evaluation is bit-identical in a
+    batch and alone; a trial's gradient is kept only when the trial is
+    accepted).  Returns one ``(z, J, hist, iterations)`` per problem."""
+    if any(p.ou is not None for p in probs):
+        raise ValueError("batched_projected_lbfgs: the prior terms are not supported")
+    lanes = [_Lane(p, z0, iters, memory) for p, z0 in zip(probs, z0s)]
+    jobs = [ln.job() for ln in lanes]
+    while True:
+        for ln in lanes:
+            ln.load()
+        pat.batch_gradient(jobs, nstreams)
+        for ln in lanes:
+            if not ln.done:
+                ln.evaluated(c1, max_halvings)
+        if all(ln.done for ln in lanes):
+            break
+        for ln in lanes:
+            if ln.done:
+                ln.zt = ln.z                     # re-evaluate the final point (keeps the batch fixed)
+    if any(ln.zt is not ln.z for ln in lanes):
+        # a lane that ended on a rejected trial: evaluate every final point
+        # once more, so that each problem's buffers (p0 gradient, data,
+        # residual) hold its final iterate's values, as after the one-problem
+        # driver
+        for ln in lanes:
+            ln.zt = ln.z
+            ln.load()
+        pat.batch_gradient(jobs, nstreams)
+    # iterations as ``projected_lbfgs`` counts them (a final iteration that
+    # found no acceptable step counts)
+    return [(ln.z, ln.J, ln.hist, ln.it if ln.it >= ln.iters else ln.it + 1) for ln in lanes]
+
+
 def lbfgs_state(prob) -> Dict:
     """The iterate and the stored pairs after the last ``projected_lbfgs`` run
     on ``prob`` (device tensors; for ``save_state`` and resuming)."""

@@ -217,3 +217,40 @@ def test_resume_gives_the_uninterrupted_result(tmp_path):
              Y=saved["Y"], levels=np.array([coarse.grid.nx, fine.grid.nx]))
     res2 = recon.multigrid([coarse, fine], *args, iters=6, resume=str(st2))
     assert torch.equal(res2["c"], ref["c"]) and torch.equal(res2["p0"], ref["p0"])
+
+
+@pytest.mark.parametrize("max_halvings", [20, 1])
+def test_batched_lbfgs_equals_one_problem_at_a_time(max_halvings):
+    """Several reconstructions in lockstep (one batched evaluation per round,
+    shared launches) take exactly the iterates each takes alone, and leave
+    each problem's p0 gradient at its final iterate; with one trial per line
+    search some problems stop early on a rejected trial."""
+    import torch
+    from paper_2505_08482_amd import pat, recon
+    specs = [(64, 2, 90, 1), (64, 1, 70, 2), (96, 2, 80, 3)]
+    probs, z0s, ref = [], [], []
+    for n, K, nt, case in specs:
+        wl = I.config2(n=n, K=K, nt=nt)
+        c_t, p_t = I.phantoms(wl, 2, case=case)
+        clean, _ = kspace.forward(wl.grid, wl.sensors, c_t, p_t, record=False)
+        y, sigma = I.add_noise(clean, seed=90 + case)
+        yt = torch.from_numpy(y.astype(np.float32)).cuda()
+        wt = torch.from_numpy((1.0 / sigma).astype(np.float32)).cuda()
+        prob = recon.Problem(wl, yt, wt, 1400.0, 1600.0)
+        x0 = torch.zeros(prob.n, dtype=torch.float32, device="cuda")
+        x0[prob.K * prob.N:] = 1500.0
+        z0 = torch.empty_like(x0)
+        pat.mul(x0, prob.inv_scale, z0)
+        announce(f"alone {n} K={K} max_halvings={max_halvings}")
+        z, J, hist, nit = recon.projected_lbfgs(prob, z0, iters=6, max_halvings=max_halvings)
+        ref.append((z.clone(), list(hist), nit, prob.gp0.clone()))
+        probs.append(prob)
+        z0s.append(z0)
+    announce("lockstep")
+    out = recon.batched_projected_lbfgs(probs, z0s, iters=6, max_halvings=max_halvings)
+    for (z, J, hist, nit), (zr, hr, nr, gr), p in zip(out, ref, probs):
+        assert nit == nr and hist == hr, (hist, hr)
+        assert torch.equal(z, zr)
+        assert torch.equal(p.gp0, gr)       # the final iterate's p0 gradient
+    for p in probs:
+        p.close()
