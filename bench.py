@@ -487,6 +487,9 @@ def main() -> int:
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint interval (0 = store the whole history)")
     ap.add_argument("--tile", default="auto", choices=("auto", "0", "8"),
                     help="column-pass tile width (auto: the autotuner's choice)")
+    ap.add_argument("--col-order", default="auto", choices=("auto", "0", "1", "2"),
+                    help="column-pass transform order (0 together, 1 one after the other, 2 split over two "
+                         "half-blocks; auto: the autotuner's choice)")
     ap.add_argument("--trace-every", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=100)
@@ -516,12 +519,15 @@ def main() -> int:
     g = wl.grid
     c_true, p0 = I.phantoms(wl, 3)
     plan = pat.Plan(g, wl.K, wl.sensors)
-    if args.tile == "auto":
+    tile, col_seq = 0, 0
+    if args.tile == "auto" or args.col_order == "auto":
         from paper_2505_08482_amd import tune
         cfg = tune.launch_for(g.nx, wl.K)    # the committed table for this GPU type, else measured
         tile, col_seq = cfg["tile"], cfg["seq"]
-    else:
-        tile, col_seq = int(args.tile), 0
+    if args.tile != "auto":
+        tile = int(args.tile)
+    if args.col_order != "auto":
+        col_seq = int(args.col_order)
     plan.set_tile(tile)
     plan.set_col_order(col_seq)
     t_c_true = torch.from_numpy(c_true.astype(np.float32)).to(dev)
@@ -598,7 +604,7 @@ def main() -> int:
         "config": {"workload": wl.name, "grid": f"{g.nx}x{g.ny}", "K": wl.K, "nt": g.nt, "sensors": wl.m,
                    "dx_m": g.dx, "dt_s": g.dt, "pml": g.pml,
                    "history": "store-all" if args.ckpt == 0 else f"checkpoint every {args.ckpt}",
-                   "column_tile": tile or "default", "column_order": "sequential" if col_seq else "together",
+                   "column_tile": tile or "default", "column_order": ("together", "sequential", "split")[col_seq],
                    "step": "recorded forward + misfit + adjoint gradient (g_p0 for all K, g_c)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

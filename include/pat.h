@@ -210,10 +210,12 @@ int pat_plan_set_tile(pat_plan* plan, int32_t col_tile);
  * transforms a thread holds advance stage by stage together (shared
  * barriers; the default), 1 = one after the other (the first array's loads
  * issued first, so its transform starts while the second array's loads land,
- * and its result is stored while the second is transformed).  A tuning knob
- * (results are identical); captured step graphs of the plan are discarded
- * when it changes.  PAT_EINVAL for other values. */
-int pat_plan_set_col_order(pat_plan* plan, int32_t sequential);
+ * and its result is stored while the second is transformed), 2 = the two
+ * arrays of a pass on the two halves of a block of twice the threads (one
+ * transform per thread, twice the waves per launch; always the default
+ * column tile).  A tuning knob (results are identical); captured step graphs
+ * of the plan are discarded when it changes.  PAT_EINVAL for other values. */
+int pat_plan_set_col_order(pat_plan* plan, int32_t order);
 
 /* One independent problem of a batch: everything a forward + misfit +
  * adjoint evaluation needs (as for pat_forward / pat_misfit /

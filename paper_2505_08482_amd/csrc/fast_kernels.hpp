@@ -44,6 +44,10 @@ template <class T>
 __device__ __forceinline__ T* at_byte(T* base, unsigned byte_off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
 }
+template <class T>
+__device__ __forceinline__ const T* at_byte(const T* base, unsigned byte_off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
 
 // LDS position of element i: one pad slot per 8 keeps the radix-8 exchanges
 // (stride-8 writes, stride-1 reads) free of bank conflicts within a transform.
@@ -94,21 +98,29 @@ __device__ __forceinline__ void rstage(float2 (*v)[8], const float2* w, float2* 
         for (int r = 0; r < R; ++r) v[t][b + r * B] = y[t][b][r];
     return;
   }
+  // Padded positions as one lane-dependent base plus compile-time offsets
+  // (immediate offsets of the shared-memory instructions, no address register
+  // per element): phys(base + r NS) = phys(base) + r NS 9/8 when NS is a
+  // multiple of 8, and phys(8 j + r) = phys(8 j) + r for r < 8; likewise
+  // phys(q + T m) = phys(q) + T m 9/8 when T is a multiple of 8.
+  static_assert(NS % 8 == 0 || (NS == 1 && R == 8), "padded stage offsets");
+  constexpr int WSTEP = NS % 8 == 0 ? NS + NS / 8 : 1;
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = q + T * b;
-    const int base = (j / NS) * NS * R + (j % NS);
+    const int pb = phys((j / NS) * NS * R + (j % NS));
 #pragma unroll
     for (int t = 0; t < NV; ++t)
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[t][phys(base + r * NS)] = y[t][b][r];
+      for (int r = 0; r < R; ++r) lds[t][pb + r * WSTEP] = y[t][b][r];
   }
   __syncthreads();
+  const int pq = phys(q);
 #pragma unroll
   for (int t = 0; t < NV; ++t)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) v[t][m] = lds[t][phys(q + T * m)];
+    for (int m = 0; m < 8; ++m) v[t][m] = lds[t][T % 8 == 0 ? pq + (T + T / 8) * m : phys(q + T * m)];
 }
 
 template <int N, typename L> struct RegFft;
@@ -121,11 +133,13 @@ template <int N, int R1, int R2, int R3> struct RegFft<N, RList<R1, R2, R3>> {
 #pragma unroll
     for (int b = 0; b < 8 / R2; ++b)
 #pragma unroll
-      for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] = tw[(r * ((q + T * b) % NS2)) * (N / (NS2 * R2))];
+      for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] =
+            *at_byte(tw, (unsigned)((r * ((q + T * b) % NS2)) * (N / (NS2 * R2))) * 8u);
 #pragma unroll
     for (int b = 0; b < 8 / R3; ++b)
 #pragma unroll
-      for (int r = 1; r < R3; ++r) w3[b * (R3 - 1) + r - 1] = tw[(r * ((q + T * b) % NS3)) * (N / (NS3 * R3))];
+      for (int r = 1; r < R3; ++r) w3[b * (R3 - 1) + r - 1] =
+            *at_byte(tw, (unsigned)((r * ((q + T * b) % NS3)) * (N / (NS3 * R3))) * 8u);
   }
   template <int DIR, int NV>
   __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
@@ -142,7 +156,8 @@ template <int N, int R1, int R2> struct RegFft<N, RList<R1, R2>> {
 #pragma unroll
     for (int b = 0; b < 8 / R2; ++b)
 #pragma unroll
-      for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] = tw[(r * ((q + T * b) % NS2)) * (N / (NS2 * R2))];
+      for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] =
+            *at_byte(tw, (unsigned)((r * ((q + T * b) % NS2)) * (N / (NS2 * R2))) * 8u);
   }
   template <int DIR, int NV>
   __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
@@ -832,6 +847,23 @@ __global__ __launch_bounds__(64 * KB) void k_adj_final(Tables tb, const float* _
   fast::k_adj_final_body<N, KB>(blockIdx.x, tb, c, p0, resid0, rhx, rhy, gcg, gp0, SA);
 }
 
+// Spectral products of the column passes with contraction off: every product
+// and sum rounds on its own, so the column-pass variants (which place these
+// products differently over threads and registers) form the same bits.
+__device__ __forceinline__ float2 sp_mul(float2 a, float2 b) {
+#pragma clang fp contract(off)
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 sp_add(float2 a, float2 b) {
+#pragma clang fp contract(off)
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+// o0 + i oN
+__device__ __forceinline__ float2 sp_join(float2 o0, float2 oN) {
+#pragma clang fp contract(off)
+  return make_float2(o0.x - oN.y, o0.y + oN.x);
+}
+
 // ===========================================================================
 // Column pass (transform length NY = N), nx/2 folded columns, TC per block
 // ===========================================================================
@@ -851,7 +883,7 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
   constexpr bool TWO_OUT = MODE != COL_SUMM;
   __shared__ float2 LA[TC * P];
   __shared__ float2 LB[(TWO_IN || TWO_OUT) ? TC * P : 1];
-  const int K = tb.K, nx = tb.nx, nhf = nx / 2, nh = tb.nh;
+  const int K = tb.K, nx = tb.nx, nhf = nx / 2;
   const int k = bid % K, c0 = (bid / K) * TC;
   const int tid = threadIdx.x, cl = tid % TC, q = tid / TC, cx = c0 + cl;
   const bool ok = cx < nhf;
@@ -886,15 +918,20 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
   float2 eyv[8];
   const float2 exv = ext[col0 ? 0 : (ok ? cx : 0)];
   const float2 exN = ext[nx / 2];
-  // every lane loads the Nyquist-column kappa too (used by the DC + i Nyquist
-  // column only): a load under a lane condition would be waited for inside
-  // its branch, serialising the prologue of the blocks that hold column 0
+  // kappa is column-major, so a wave reads 64-byte runs of it; the Nyquist
+  // column's kappa only in the block that holds column 0 (a block-uniform
+  // branch: no lane waits inside a divergent branch)
+  const float* const kcol = tb.kappa + (size_t)(ok ? cx : 0) * N;
+  const float* const kcolN = tb.kappa + (size_t)(nx / 2) * N;
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     const int e = q + T * m;
-    kap[m] = tb.kappa[(size_t)e * nh + (ok ? cx : 0)] * scale;
-    kapN[m] = tb.kappa[(size_t)e * nh + nx / 2] * scale;
+    kap[m] = kcol[e] * scale;
     eyv[m] = eyt[e];
+  }
+  if (c0 == 0) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) kapN[m] = kcolN[q + T * m] * scale;
   }
   float2* LL[2] = {LA + cl * P, LB + cl * P};
   if (TWO_IN && SEQ) {
@@ -934,19 +971,19 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
         }
         float2 o0, oN, p0_, pN;
         if (MODE == COL_GRAD1) {
-          o0 = cscale(cmul(A0, exv), k0); oN = cscale(cmul(AN, exN), kN);
-          p0_ = cscale(cmul(A0, ey), k0); pN = cscale(cmul(AN, ey), kN);
+          o0 = cscale(sp_mul(A0, exv), k0); oN = cscale(sp_mul(AN, exN), kN);
+          p0_ = cscale(sp_mul(A0, ey), k0); pN = cscale(sp_mul(AN, ey), kN);
         } else if (MODE == COL_PAIRP || MODE == COL_PAIRM) {
-          o0 = cscale(cmul(A0, exv), k0); oN = cscale(cmul(AN, exN), kN);
-          p0_ = cscale(cmul(B0, ey), k0); pN = cscale(cmul(BN, ey), kN);
+          o0 = cscale(sp_mul(A0, exv), k0); oN = cscale(sp_mul(AN, exN), kN);
+          p0_ = cscale(sp_mul(B0, ey), k0); pN = cscale(sp_mul(BN, ey), kN);
         } else {
-          o0 = cscale(cadd(cmul(A0, exv), cmul(B0, ey)), k0);
-          oN = cscale(cadd(cmul(AN, exN), cmul(BN, ey)), kN);
+          o0 = cscale(sp_add(sp_mul(A0, exv), sp_mul(B0, ey)), k0);
+          oN = cscale(sp_add(sp_mul(AN, exN), sp_mul(BN, ey)), kN);
           p0_ = o0; pN = oN;
         }
         // recombine: out = o0 + i oN
-        a[0][m] = make_float2(o0.x - oN.y, o0.y + oN.x);
-        if (TWO_OUT) a[1][m] = make_float2(p0_.x - pN.y, p0_.y + pN.x);
+        a[0][m] = sp_join(o0, oN);
+        if (TWO_OUT) a[1][m] = sp_join(p0_, pN);
       }
     }
   }
@@ -955,13 +992,13 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
     for (int m = 0; m < 8; ++m) {
       const float2 x0 = a[0][m];
       if (MODE == COL_GRAD1) {
-        a[0][m] = cscale(cmul(x0, exv), kap[m]);
-        a[1][m] = cscale(cmul(x0, eyv[m]), kap[m]);
+        a[0][m] = cscale(sp_mul(x0, exv), kap[m]);
+        a[1][m] = cscale(sp_mul(x0, eyv[m]), kap[m]);
       } else if (MODE == COL_PAIRP || MODE == COL_PAIRM) {
-        a[0][m] = cscale(cmul(x0, exv), kap[m]);
-        a[1][m] = cscale(cmul(a[1][m], eyv[m]), kap[m]);
+        a[0][m] = cscale(sp_mul(x0, exv), kap[m]);
+        a[1][m] = cscale(sp_mul(a[1][m], eyv[m]), kap[m]);
       } else {
-        a[0][m] = cscale(cadd(cmul(x0, exv), cmul(a[1][m], eyv[m])), kap[m]);
+        a[0][m] = cscale(sp_add(sp_mul(x0, exv), sp_mul(a[1][m], eyv[m])), kap[m]);
       }
     }
   }
@@ -994,6 +1031,149 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
   // that follow, not by this one), after the stores so that no block waits
   // for it before its own loads
   if (step && bid == 0 && threadIdx.x == 0) *step += delta;
+}
+
+// Split column pass: the two arrays of a pass on the two halves of a block
+// (twice the threads of k_col, one transform per thread), so that a launch
+// holds twice the waves.  Array A on threads [0, TC*T), array B on
+// [TC*T, 2*TC*T).  Single-input pass (COL_GRAD1): both halves transform A and
+// each applies its own direction's factor.  Single-output pass (COL_SUMM): the
+// B half hands its weighted spectrum to the A half through shared memory and
+// then runs the same inverse transform on its registers (result discarded), so
+// that both halves pass the same barriers.  Same arithmetic as k_col.
+template <int N, int MODE, int TC = Cfg<N>::TC>
+__device__ __forceinline__ void k_cols_body(const int bid, const Tables& tb, float2* __restrict__ SA,
+                                            float2* __restrict__ SB, float scale, int32_t* __restrict__ step,
+                                            int32_t delta) {
+  constexpr int T = Cfg<N>::T, P = LdsCol<N, TC>::P, HALF = TC * T;
+  static_assert(HALF % 64 == 0, "each half is whole waves");
+  static_assert((TC == 4 && P % 16 == 4) || (TC == 8 && P % 16 == 2) || (TC >= 16 && P % 2 == 1),
+                "column pitch");
+  constexpr bool TWO_IN = MODE != COL_GRAD1;
+  constexpr bool SUMM = MODE == COL_SUMM;
+  __shared__ float2 LS[2][TC * P];
+  __shared__ float2 Q0[SUMM ? N : 1];   // COL_SUMM: B's products of column 0, DC part
+  __shared__ float2 QN[SUMM ? N : 1];   // and Nyquist part
+  __shared__ float2 QA[SUMM ? N : 1];   // A's Nyquist part of column 0
+  const int K = tb.K, nx = tb.nx, nhf = nx / 2;
+  const int k = bid % K, c0 = (bid / K) * TC;
+  const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.x / HALF);   // 0: array A, 1: array B
+  const int tid = (int)threadIdx.x - s * HALF, cl = tid % TC, q = tid / TC, cx = c0 + cl;
+  const bool ok = cx < nhf;
+  const size_t koff = (size_t)k * N * nhf;
+  float2* const src = ((TWO_IN && s) ? SB : SA) + koff;
+  float2* const dst = (s ? SB : SA) + koff;
+  const unsigned lane_b = ((unsigned)q * nhf + (ok ? cx : 0)) * 8u, row_b = (unsigned)T * nhf * 8u;
+  Fft<N> fft;
+  fft.init(tb.tw_y, q);
+  float2 a[1][8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) a[0][m] = *at_byte(src, lane_b + m * row_b);
+  float2* const L = LS[s] + cl * P;
+  float2* LL[1] = {L};
+  fft.template run<-1, 1>(a, LL, q);
+  // spectral factors, loaded after the forward transform (fewer live
+  // registers; other waves hide the latency): this half's direction factor
+  // (x: per column, y: per row) and kappa
+  constexpr bool PLUS = MODE == COL_GRAD1 || MODE == COL_PAIRP;
+  const float2* eyt = PLUS ? tb.ey_p : tb.ey_m;
+  const float2* ext = PLUS ? tb.ex_p : tb.ex_m;
+  const bool col0 = c0 == 0 && cl == 0;   // DC + i Nyquist column
+  float kap[8];
+  float2 fac[8];
+  float kap_n[SUMM ? 8 : 1];   // COL_SUMM, half A, column 0: kappa of the Nyquist part
+  // branch-free per half: half A reads its column's x factor (the same
+  // address for every m), half B the y factor of each of its rows
+  const float2* const ft = s ? eyt : ext;
+  const unsigned f_b = (s ? (unsigned)q : (unsigned)(ok ? cx : 0)) * 8u, f_step = s ? (unsigned)T * 8u : 0u;
+  // kappa is column-major: a wave reads 64-byte runs of it
+  const unsigned k_b = ((unsigned)(ok ? cx : 0) * N + q) * 4u, k_step = (unsigned)T * 4u;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    kap[m] = *at_byte(tb.kappa, k_b + m * k_step) * scale;
+    fac[m] = *at_byte(ft, f_b + m * f_step);
+  }
+  // own-direction products, in place: x direction (half A), y direction
+  // (half B), times kappa; column 0 splits into its DC and Nyquist parts by
+  // conjugate symmetry along y.  COL_SUMM: the B half stores its products
+  // unscaled (column 0's two parts in Q0 and QN, the other columns over its
+  // own transform positions, which no other thread reads any more) and the A
+  // half adds them before scaling.
+  if (c0 == 0) {   // block-uniform
+    const float2 exN = ext[nx / 2];
+    const unsigned n_b = ((unsigned)(nx / 2) * N + q) * 4u;
+    float kapN[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) kapN[m] = *at_byte(tb.kappa, n_b + m * k_step) * scale;
+    __syncthreads();
+    if (cl == 0) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) L[phys(q + T * m)] = a[0][m];
+    }
+    __syncthreads();
+    if (cl == 0) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int e = q + T * m, ep = (N - e) & (N - 1);
+        const float2 Z = a[0][m], Zp = L[phys(ep)];
+        const float2 X0 = make_float2(0.5f * (Z.x + Zp.x), 0.5f * (Z.y - Zp.y));
+        const float2 XN = make_float2(0.5f * (Z.y + Zp.y), -0.5f * (Z.x - Zp.x));
+        const float2 u0 = sp_mul(X0, fac[m]), uN = sp_mul(XN, s ? fac[m] : exN);
+        if (SUMM && s) {
+          Q0[e] = u0;
+          QN[e] = uN;
+        } else if (!SUMM) {
+          const float2 o0 = cscale(u0, kap[m]), oN = cscale(uN, kapN[m]);
+          a[0][m] = sp_join(o0, oN);
+        } else {
+          a[0][m] = u0;                 // A's parts, combined below
+          QA[e] = uN;
+          kap_n[m] = kapN[m];
+        }
+      }
+    }
+  }
+  if (!col0) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const float2 u = sp_mul(a[0][m], fac[m]);
+      if (SUMM && s)
+        L[phys(q + T * m)] = u;
+      else if (!SUMM)
+        a[0][m] = cscale(u, kap[m]);
+      else
+        a[0][m] = u;
+    }
+  }
+  if (SUMM) {
+    __syncthreads();
+    if (!s) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int e = q + T * m;
+        if (col0) {
+          const float2 o0 = cscale(sp_add(a[0][m], Q0[e]), kap[m]);
+          const float2 oN = cscale(sp_add(QA[e], QN[e]), kap_n[m]);
+          a[0][m] = sp_join(o0, oN);
+        } else {
+          a[0][m] = cscale(sp_add(a[0][m], LS[1][cl * P + phys(e)]), kap[m]);
+        }
+      }
+    }
+  }
+  fft.template run<+1, 1>(a, LL, q);
+  if (ok && (!SUMM || !s)) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) *at_byte(dst, lane_b + m * row_b) = a[0][m];
+  }
+  if (step && bid == 0 && threadIdx.x == 0) *step += delta;
+}
+
+template <int N, int MODE, int TC = Cfg<N>::TC>
+__global__ __launch_bounds__(2 * TC * Cfg<N>::T, 4) void k_cols(Tables tb, float2* __restrict__ SA,
+                                                                 float2* __restrict__ SB, float scale,
+                                                                 int32_t* __restrict__ step, int32_t delta) {
+  fast::k_cols_body<N, MODE, TC>(blockIdx.x, tb, SA, SB, scale, step, delta);
 }
 
 template <int N, int MODE, int TC = Cfg<N>::TC, bool SEQ = false>

@@ -99,7 +99,8 @@ struct pat_plan {
   int K = 0, m = 0, nh = 0;
   bool fast = false;         // register-resident power-of-two passes (folded spectra)
   int col_tile = 0;          // column-pass tile width: 0 = default for the length, or 8
-  bool col_seq = false;      // column pass: the two transforms of a thread one after the other
+  int col_order = 0;         // column pass: 0 two transforms per thread together, 1 one after the other,
+                             // 2 the two arrays on two halves of the block
   bool check_finite = false; // check mode: scan outputs, return PAT_ENONFINITE on NaN / Inf
   int32_t* flag = nullptr;   // device flag of the check mode
   int kb = 1;                // datasets per block of the fast adjoint density / closing passes
@@ -297,13 +298,16 @@ int launch_col(const pat_plan* p, hipStream_t st, float2* SA, float2* SB, float 
     switch (p->g.ny) {
 #define X(N)                                                                                                   \
   case N:                                                                                                      \
-    if (p->col_tile == 8 && p->col_seq)                                                                         \
+    if (p->col_order == 2)                                                                                      \
+      PAT_LAUNCH((fast::k_cols<N, MODE>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),                              \
+                 dim3(2 * fast::Cfg<N>::TC * fast::Cfg<N>::T), 0, st, p->tb, SA, SB, scale, step, delta);      \
+    else if (p->col_tile == 8 && p->col_order == 1)                                                             \
       PAT_LAUNCH((fast::k_col<N, MODE, 8, true>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st, \
                  p->tb, SA, SB, scale, step, delta);                                                             \
     else if (p->col_tile == 8)                                                                                  \
       PAT_LAUNCH((fast::k_col<N, MODE, 8>), dim3(fcols_blocks(p, 8)), dim3(8 * fast::Cfg<N>::T), 0, st,        \
                  p->tb, SA, SB, scale, step, delta);                                                             \
-    else if (p->col_seq)                                                                                        \
+    else if (p->col_order == 1)                                                                                 \
       PAT_LAUNCH((fast::k_col<N, MODE, fast::Cfg<N>::TC, true>), dim3(fcols_blocks(p, fast::Cfg<N>::TC)),     \
                  dim3(fast::Cfg<N>::TC * fast::Cfg<N>::T), 0, st, p->tb, SA, SB, scale, step, delta);          \
     else                                                                                                        \
@@ -1282,7 +1286,7 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
     for (int i = 0; i < nh; ++i) {
       const double kx = wavenumber(i, nx, g->dx);
       const double arg = g->c_ref * std::sqrt(kx * kx + ky * ky) * g->dt / 2.0;
-      kap[(size_t)e * nh + i] = (float)(arg == 0.0 ? 1.0 : std::sin(arg) / arg);
+      kap[(size_t)i * ny + e] = (float)(arg == 0.0 ? 1.0 : std::sin(arg) / arg);   // column-major: [nh][ny]
     }
   }
   std::vector<float> ax, asx, ax2, asx2, wfx, ay, asy, ay2, asy2, wfy;
@@ -1699,11 +1703,11 @@ int pat_plan_set_tile(pat_plan* p, int32_t col_tile) {
   return PAT_OK;
 }
 
-int pat_plan_set_col_order(pat_plan* p, int32_t sequential) {
-  if (!p || (sequential != 0 && sequential != 1)) return PAT_EINVAL;
-  if ((sequential != 0) != p->col_seq) {   // captured graphs hold the old kernels
+int pat_plan_set_col_order(pat_plan* p, int32_t order) {
+  if (!p || order < 0 || order > 2) return PAT_EINVAL;
+  if (order != p->col_order) {   // captured graphs hold the old kernels
     drop_graphs(p);
-    p->col_seq = sequential != 0;
+    p->col_order = order;
   }
   return PAT_OK;
 }

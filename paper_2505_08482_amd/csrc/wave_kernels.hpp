@@ -60,7 +60,7 @@ struct Tables {
   const float2* ex_m;   // [nh] kx * (i exp(-i kx dx/2))
   const float2* ey_p;   // [ny]
   const float2* ey_m;   // [ny]
-  const float* kappa;   // [ny][nh] sinc(c_ref |k| dt / 2)
+  const float* kappa;   // [nh][ny] sinc(c_ref |k| dt / 2), column-major: the column passes read it along y
   const float* ax;      // [nx] exp(-alpha dt/2) at grid points
   const float* asx;     // [nx] at staggered points (i + 1/2)
   const float* ax2;     // [nx] ax^2
@@ -364,7 +364,7 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
     if (cx < nh) {
       const float2 exp_ = tb.ex_p[cx], exm = tb.ex_m[cx];
       for (int e = q; e < NY; e += C::T) {
-        const float kap = tb.kappa[(size_t)e * nh + cx] * scale;
+        const float kap = tb.kappa[(size_t)cx * NY + e] * scale;
         const float2 a = A[tr][e];
         if (MODE == COL_GRAD1) {
           A[tr][e] = cscale(cmul(a, exp_), kap);

@@ -188,9 +188,10 @@ class Plan:
         """Column-pass tile width (0 = default, 8); results do not change."""
         _check(lib().pat_plan_set_tile(self._h, int(col_tile)), "pat_plan_set_tile")
 
-    def set_col_order(self, sequential: int):
-        """Column-pass transform order (0 = together, 1 = one after the other); results do not change."""
-        _check(lib().pat_plan_set_col_order(self._h, int(sequential)), "pat_plan_set_col_order")
+    def set_col_order(self, order: int):
+        """Column-pass transform order (0 = together, 1 = one after the other, 2 = the two arrays on two
+        halves of a block); results do not change."""
+        _check(lib().pat_plan_set_col_order(self._h, int(order)), "pat_plan_set_col_order")
 
     def workspace_size(self, ckpt_every: int = 0) -> int:
         b = ctypes.c_size_t()

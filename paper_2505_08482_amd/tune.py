@@ -1,6 +1,7 @@
 """Autotuner of the launch configuration: per grid size and dataset count, the
 column-pass tile width (4 or 8 columns per block) and transform order (a
-thread's two transforms together or one after the other); per batch, the
+thread's two transforms together or one after the other, or the two arrays
+on two halves of a block); per batch, the
 stream count.  Measurements are taken on the GPU with short time axes and
 cached per (grid, K, GPU architecture) in a JSON file under the user cache
 directory (``$PAT_TUNE_CACHE`` overrides the path); choices measured once per
@@ -79,7 +80,7 @@ def _time_gradient(plan, c, p0, y, w, reps: int = 3) -> float:
 
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
-CANDIDATES = ((0, 0), (8, 0), (0, 1), (8, 1))   # (column tile, column transform order)
+CANDIDATES = ((0, 0), (8, 0), (0, 1), (8, 1), (0, 2))   # (column tile, column transform order)
 
 
 def _table() -> Dict:
@@ -93,8 +94,9 @@ def _table() -> Dict:
 
 def launch_for(n: int, K: int, nt_probe: int = 200, force: bool = False) -> Dict[str, int]:
     """Fastest column-pass configuration for an n x n grid with K datasets:
-    ``{"tile": 0 | 8, "seq": 0 | 1}`` (columns per block, and whether a
-    thread's two column transforms run together or one after the other).
+    ``{"tile": 0 | 8, "seq": 0 | 1 | 2}`` (columns per block, and whether a
+    thread's two column transforms run together or one after the other, or
+    the two arrays run on two halves of a block of twice the threads).
     Taken from the committed table for this architecture, else from the user
     cache, else measured (every candidate computes the same bits)."""
     import torch

@@ -81,11 +81,12 @@ def test_batch_equals_single_runs_bitwise():
 @pytest.mark.parametrize("n, K", [(256, 2), (512, 8), (128, 3)])
 def test_column_launch_configuration_changes_no_bit(n, K):
     """Every candidate of the tuner (column tile 4 or 8, the two transforms of
-    a thread together or one after the other) gives the same bits."""
+    a thread together or one after the other, the two arrays on two halves of
+    a block) gives the same bits."""
     job = _job(n, K, 60, 9)
     announce(f"column configurations {n} K={K}")
     ref = _single(job)
-    for tile, seq in ((8, 0), (0, 1), (8, 1)):
+    for tile, seq in ((8, 0), (0, 1), (8, 1), (0, 2)):
         job["plan"].set_tile(tile)
         job["plan"].set_col_order(seq)
         out = _single(job)
