@@ -868,10 +868,11 @@ __device__ __forceinline__ float2 sp_join(float2 o0, float2 oN) {
 // Column pass (transform length NY = N), nx/2 folded columns, TC per block
 // ===========================================================================
 // TC: columns per block (the default Cfg<N>::TC, or a width picked by the tuner).
-// SEQ: the two transforms of a thread run one after the other (loads of the
-// first array issued first, so its transform starts while the second array's
-// loads land, and the first output is stored while the second is transformed)
-// instead of stage by stage together (shared barriers).  Same arithmetic.
+// SEQ: the two transforms of a thread run one after the other (the second
+// array's loads issued once the first array's data have arrived, so that its
+// transform runs while the second array streams in, and the first output is
+// stored while the second is transformed) instead of stage by stage together
+// (shared barriers).  Same arithmetic.
 template <int N, int MODE, int TC = Cfg<N>::TC, bool SEQ = false>
 __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, float2* __restrict__ SA,
                                            float2* __restrict__ SB, float scale, int32_t* __restrict__ step,
@@ -898,6 +899,11 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
 #pragma unroll
     for (int m = 0; m < 8; ++m) a[0][m] = *at_byte(colA, lane_b + m * row_b);
     if (TWO_IN) {
+      // staged: the second array's loads issue once the first array's data
+      // have arrived, so that they stream in while the first is transformed
+      // (loads issued together arrive interleaved, and neither transform
+      // could start before the end of both)
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
       for (int m = 0; m < 8; ++m) a[1][m] = *at_byte(colB, lane_b + m * row_b);
     }

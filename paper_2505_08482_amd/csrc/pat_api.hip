@@ -1324,8 +1324,8 @@ int pat_plan_create(const pat_grid* g, int32_t K, int32_t m, const double* senso
   p->nh = nh;
   p->fast = fast_size(nx) && fast_size(ny) && !std::getenv("PAT_GENERIC_KERNELS");
   p->nhs = p->fast ? nx / 2 : nh;
-  // 4 datasets per block: g_c traffic 2 B/pt instead of 8; 8 per block (one
-  // block per CU at 107 KB of LDS) measured no faster at 512^2 x 8
+  // 4 datasets per block: g_c traffic 2 B/pt instead of 8; 1, 2 and 8 per
+  // block measured slower at 512^2 x 8
   p->kb = !p->fast ? 1 : (K >= 4 ? 4 : (K >= 2 ? 2 : 1));
   p->gsl = (K + p->kb - 1) / p->kb;
   if (hipMalloc(&p->dev, total) != hipSuccess) {

@@ -589,7 +589,7 @@ def evaluate_case(net: Optional[UNet], case: int, K: int = 8, coarse_iters: int 
         levels = [I.config3_level(n, K=K) for n in (COARSE_N, 256, FINE_N)]
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out = recon.multigrid(levels, y, dt, w, truth, iters=coarse_iters)
+        out = recon.multigrid(levels, y, dt, w, truth, iters=coarse_iters, target_Ec=stop)
         total = time.perf_counter() - t2
         fl = out["levels"][-1]
         its_before = sum(lv.iters for lv in out["levels"][:-1])
@@ -747,6 +747,48 @@ def time_network(B: int = 4, steps: int = 5, H: int = FINE_N, W: int = FINE_N) -
             "forward_GFLOP": round(ff / 1e9, 2), "train_GFLOP": round(ft / 1e9, 2)}
 
 
+RUNS = (("plain_multigrid", "plain multigrid 128 -> 256 -> 512"),
+        ("interpolated", "coarse level, then 512^2 from the interpolated coarse iterate"),
+        ("learned", "coarse level, then 512^2 from the network's proposal"))
+
+
+def summarize(rows: Sequence[Dict], targets: Sequence[float] = (2.0, 1.0)) -> Tuple[Dict, str]:
+    """Per start (plain multigrid, interpolated, learned) over the evaluated
+    cases: fine-level start E_c (mean, median), and per target the cases that
+    reach it with the mean and median wall time and iterations to it.  Returns
+    the figures and a markdown table of them."""
+    out: Dict = {"cases": len(rows)}
+    lines = ["| run | fine-start E_c mean / median | " + " | ".join(
+        f"reaches {tg:g} % | s to {tg:g} % mean / median | iterations to {tg:g} % mean" for tg in targets) + " |",
+        "|---|---:|" + "---:|---:|---:|" * len(targets)]
+    for run, label in RUNS:
+        have = [r for r in rows if run in r]
+        if not have:
+            continue
+        if run == "plain_multigrid":
+            starts = [r[run]["E_c"][0] for r in have if r[run]["E_c"]]
+        else:
+            starts = [r[run]["E_c_start"] for r in have]
+        fig = {"E_c_start_mean": round(float(np.mean(starts)), 3), "E_c_start_median": round(float(np.median(starts)), 3)}
+        cells = [f"{fig['E_c_start_mean']:.2f} % / {fig['E_c_start_median']:.2f} %"]
+        for tg in targets:
+            hits = [r[run]["to_target"][f"{tg:g}"] for r in have]
+            ok = [h for h in hits if h is not None]
+            sec = [h["seconds"] for h in ok]
+            its = [h["iterations"] for h in ok]
+            fig[f"{tg:g}"] = {"reached": len(ok), "of": len(have),
+                              "seconds_mean": round(float(np.mean(sec)), 2) if ok else None,
+                              "seconds_median": round(float(np.median(sec)), 2) if ok else None,
+                              "iterations_mean": round(float(np.mean(its)), 1) if ok else None}
+            f = fig[f"{tg:g}"]
+            cells += [f"{len(ok)}/{len(have)}",
+                      f"{f['seconds_mean']:.2f} / {f['seconds_median']:.2f}" if ok else "-",
+                      f"{f['iterations_mean']:.1f}" if ok else "-"]
+        out[run] = fig
+        lines.append(f"| {label} | " + " | ".join(cells) + " |")
+    return out, "\n".join(lines)
+
+
 def main(argv=None) -> int:
     import argparse
     import json
@@ -776,6 +818,8 @@ def main(argv=None) -> int:
     e.add_argument("--data-grid", type=int, default=FINE_N, choices=(FINE_N, 768),
                    help="grid the phantom's data are simulated on (768: finer than the reconstruction grid)")
     e.add_argument("--out", default=None)
+    sm = sub.add_parser("summary", help="table of the runs in evaluation files written by eval --out")
+    sm.add_argument("files", nargs="+")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     if a.cmd == "gen":
@@ -814,6 +858,15 @@ def main(argv=None) -> int:
         return 0
     if a.cmd == "time":
         print(json.dumps(time_network(a.batch, a.steps)), flush=True)
+        return 0
+    if a.cmd == "summary":
+        rows = []
+        for f in a.files:
+            with open(f) as fh:
+                rows += json.load(fh)
+        fig, table = summarize(rows)
+        print(json.dumps(fig, indent=1))
+        print(table)
         return 0
     if a.cmd == "eval":
         net = load_weights(a.weights) if a.weights else None

@@ -440,7 +440,9 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
     gradient|, step length, line-search trials, E_c, seconds).  ``save_path``:
     the resumable state (``save_state``) every ``save_every`` iterations and at
     the end of every level; ``resume``: such a file, to continue an interrupted
-    run (the same levels and settings) where it stopped, with the same results."""
+    run (the same levels and settings) where it stopped, with the same results.
+    ``target_Ec`` (percent): stop on the finest level at the first iteration
+    whose E_c is at or below it (coarser levels always run ``iters``)."""
     import json
     device = y_fine.device
     results: List[LevelResult] = []
@@ -513,6 +515,8 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
                     logf.flush()
                 if save_path and (first + it + 1) % save_every == 0:
                     save_state(save_path, li, first + it + 1, prob, levels_n)
+                # the caller's target on the finest level ends the run there
+                return target_Ec is not None and li == len(levels) - 1 and Ec[-1] <= target_Ec
 
             z, J, hist, nit = projected_lbfgs(prob, z0, level_iters, memory=memory, callback=cb, state=state,
                                               log=figures.update)

@@ -39,3 +39,29 @@ def test_stored_weights_have_the_table_shapes():
             # trained from He-normal initialisation (std sqrt(2 / (9 cin))): the scale stays of that order
             assert 0.1 < w.std() / np.sqrt(2.0 / (9 * ci)) < 10.0, name
         assert f["head.w"].shape == (base,) and f["head.b"].shape == (1,)
+
+
+def test_evaluation_summary_counts_and_means():
+    """The held-out summary counts each start's cases that reach a target and
+    averages time and iterations over those only; the plain multigrid run's
+    fine-start error is its first fine-level iterate."""
+    rows = [
+        {"plain_multigrid": {"E_c": [1.5, 1.2], "to_target": {"2": {"iterations": 81, "seconds": 8.0}, "1": None}},
+         "interpolated": {"E_c_start": 2.5, "to_target": {"2": None, "1": None}},
+         "learned": {"E_c_start": 0.8, "to_target": {"2": {"iterations": 40, "seconds": 2.0},
+                                                    "1": {"iterations": 40, "seconds": 2.0}}}},
+        {"plain_multigrid": {"E_c": [0.9], "to_target": {"2": {"iterations": 81, "seconds": 10.0},
+                                                         "1": {"iterations": 81, "seconds": 10.0}}},
+         "interpolated": {"E_c_start": 1.5, "to_target": {"2": {"iterations": 40, "seconds": 3.0}, "1": None}},
+         "learned": {"E_c_start": 1.2, "to_target": {"2": {"iterations": 40, "seconds": 2.2},
+                                                    "1": {"iterations": 42, "seconds": 4.0}}}},
+    ]
+    fig, table = learned.summarize(rows)
+    assert fig["cases"] == 2
+    pm, it, ln = fig["plain_multigrid"], fig["interpolated"], fig["learned"]
+    assert pm["E_c_start_mean"] == 1.2 and pm["2"]["reached"] == 2 and pm["2"]["seconds_mean"] == 9.0
+    assert pm["1"]["reached"] == 1 and pm["1"]["seconds_mean"] == 10.0
+    assert it["2"]["reached"] == 1 and it["2"]["seconds_mean"] == 3.0 and it["1"]["reached"] == 0
+    assert it["1"]["seconds_mean"] is None
+    assert ln["1"]["reached"] == 2 and ln["1"]["iterations_mean"] == 41.0 and ln["E_c_start_median"] == 1.0
+    assert table.count("\n") == 4 and "0/2" in table
