@@ -63,8 +63,16 @@ template <int N, int TC> struct LdsCol {
   static constexpr int P = TC >= 16 ? (base | 1) : base + ((16 + want - base % 16) % 16);
 };
 
+// Row transforms of length 512 (one 64-lane wave per transform) place element
+// i at i ^ swz_key(i / 16) instead of the padded i + i/8: a permutation inside
+// each run of 16 elements under which the stage-1 writes (stride 8), the
+// stage-2 writes (two runs of 8, 64 apart) and the stride-1 reads of a 16-lane
+// group each touch 16 distinct bank pairs (the padding costs a two-way
+// conflict in every 16-lane group of every read).
+__device__ __forceinline__ int swz_key(int b) { return (b & 7) | ((b & 4) << 1); }
+
 // One register-resident Stockham stage on NV transforms at once (shared barriers).
-template <int N, int T, int R, int NS, int DIR, bool LAST, int NV>
+template <int N, int T, int R, int NS, int DIR, bool LAST, int NV, bool SWZ = false>
 __device__ __forceinline__ void rstage(float2 (*v)[8], const float2* w, float2* const* lds, int q) {
   constexpr int B = 8 / R;
   float2 y[NV][B][R];
@@ -104,18 +112,42 @@ __device__ __forceinline__ void rstage(float2 (*v)[8], const float2* w, float2* 
   // multiple of 8, and phys(8 j + r) = phys(8 j) + r for r < 8; likewise
   // phys(q + T m) = phys(q) + T m 9/8 when T is a multiple of 8.
   static_assert(NS % 8 == 0 || (NS == 1 && R == 8), "padded stage offsets");
+  static_assert(!SWZ || LAST || (T == 64 && R == 8 && (NS == 1 || NS == 8)), "swizzled stages: 512-point rows");
   constexpr int WSTEP = NS % 8 == 0 ? NS + NS / 8 : 1;
   __syncthreads();
-#pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int j = q + T * b;
-    const int pb = phys((j / NS) * NS * R + (j % NS));
+  if (SWZ) {
+    // stage 1: 8 q + r -> ((8 q) ^ (key & 8)) + (r ^ (key & 7)), key of run q/2;
+    // stage 2: base + 8 r (base = 64 (q/8) + q%8) -> (base + 8 r) ^ (12 h + r/2), h = bit 3 of q
+    const int key1 = swz_key(q >> 1), wb1 = (8 * q) ^ (key1 & 8), k7 = key1 & 7;
+    const int base2 = 64 * (q >> 3) + (q & 7), h12 = 12 * ((q >> 3) & 1);
 #pragma unroll
     for (int t = 0; t < NV; ++t)
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[t][pb + r * WSTEP] = y[t][b][r];
+      for (int r = 0; r < R; ++r) {
+        const int pos = NS == 1 ? wb1 + (r ^ k7) : (base2 + 8 * r) ^ (h12 + (r >> 1));
+        lds[t][pos] = y[t][0][r];
+      }
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = q + T * b;
+      const int pb = phys((j / NS) * NS * R + (j % NS));
+#pragma unroll
+      for (int t = 0; t < NV; ++t)
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[t][pb + r * WSTEP] = y[t][b][r];
+    }
   }
   __syncthreads();
+  if (SWZ) {
+    // q + 64 m -> 64 m + (q ^ (q/16 + 12 (m & 1)))
+    const int r0 = q ^ (q >> 4), r1 = q ^ ((q >> 4) + 12);
+#pragma unroll
+    for (int t = 0; t < NV; ++t)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[t][m] = lds[t][((m & 1) ? r1 : r0) + 64 * m];
+    return;
+  }
   const int pq = phys(q);
 #pragma unroll
   for (int t = 0; t < NV; ++t)
@@ -141,11 +173,12 @@ template <int N, int R1, int R2, int R3> struct RegFft<N, RList<R1, R2, R3>> {
       for (int r = 1; r < R3; ++r) w3[b * (R3 - 1) + r - 1] =
             *at_byte(tw, (unsigned)((r * ((q + T * b) % NS3)) * (N / (NS3 * R3))) * 8u);
   }
-  template <int DIR, int NV>
+  // SWZ: swizzled shared-memory positions (512-point rows, see swz_key)
+  template <int DIR, int NV, bool SWZ = false>
   __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
-    rstage<N, T, R1, 1, DIR, false, NV>(v, nullptr, lds, q);
-    rstage<N, T, R2, NS2, DIR, false, NV>(v, w2, lds, q);
-    rstage<N, T, R3, NS3, DIR, true, NV>(v, w3, lds, q);
+    rstage<N, T, R1, 1, DIR, false, NV, SWZ>(v, nullptr, lds, q);
+    rstage<N, T, R2, NS2, DIR, false, NV, SWZ>(v, w2, lds, q);
+    rstage<N, T, R3, NS3, DIR, true, NV, SWZ>(v, w3, lds, q);
   }
 };
 
@@ -159,8 +192,9 @@ template <int N, int R1, int R2> struct RegFft<N, RList<R1, R2>> {
       for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] =
             *at_byte(tw, (unsigned)((r * ((q + T * b) % NS2)) * (N / (NS2 * R2))) * 8u);
   }
-  template <int DIR, int NV>
+  template <int DIR, int NV, bool SWZ = false>
   __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
+    static_assert(!SWZ, "swizzled stages: 512-point rows only");
     rstage<N, T, R1, 1, DIR, false, NV>(v, nullptr, lds, q);
     rstage<N, T, R2, NS2, DIR, true, NV>(v, w2, lds, q);
   }
@@ -284,7 +318,7 @@ __device__ __forceinline__ void k_fwd_init_body(const int bid, const Tables& tb,
   __syncthreads();
   if (dpart) gather_rows<N, 64>(tb, &P[0][0], ybase, RC::ROWS, dpart + (size_t)k * tb.nt * 2 * tb.m, tid);
   float2* L[1] = {X[grp]};
-  fft.template run<-1, 1>(v, L, q);
+  fft.template run<-1, 1, N == 512>(v, L, q);
   float2* ra = SA + ((size_t)k * ny + min(y0, ny - 1)) * nhf;
   float2* rb = SA + ((size_t)k * ny + min(y1, ny - 1)) * nhf;
   if (y1 < ny) unpack_store<N>(v[0], q, lane_base, ra, rb);
@@ -334,7 +368,7 @@ __device__ __forceinline__ void k_fwd_u_body(const int bid, const Tables& tb, fl
   pay[0] = tb.asy[ok ? y0 : 0];
   pay[1] = tb.asy[ok ? y1 : 0];
   float2* L[2] = {X[grp][0], X[grp][1]};
-  fft.template run<+1, 2>(v, L, q);
+  fft.template run<+1, 2, N == 512>(v, L, q);
   // step 0 starts from u^{-1/2} = G/2 (a uniform branch, not a per-element select)
   auto update = [&](auto first_c) {
     constexpr bool F0 = decltype(first_c)::value;
@@ -364,7 +398,7 @@ __device__ __forceinline__ void k_fwd_u_body(const int bid, const Tables& tb, fl
         uyr[h][(unsigned)(q + T * m)] = v[h][m].y;
       }
   }
-  fft.template run<-1, 2>(v, L, q);
+  fft.template run<-1, 2, N == 512>(v, L, q);
   if (ok) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -429,7 +463,7 @@ __device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, 
   const bool has_g = dpart_n && (g0 + tid < g1);
   if (has_g) ge = tb.g_ent[g0 + tid];
   float2* L[2] = {X[grp][0], X[grp][1]};
-  fft.template run<+1, 2>(v, L, q);
+  fft.template run<+1, 2, N == 512>(v, L, q);
   float2 z[1][8];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -483,7 +517,7 @@ __device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, 
     }
   }
   float2* L1[1] = {X[grp][0]};
-  fft.template run<-1, 1>(z, L1, q);
+  fft.template run<-1, 1, N == 512>(z, L1, q);
   if (ok) {
     float2* ra = SA + ((size_t)k * ny + y0) * nhf;
     float2* rb = SA + ((size_t)k * ny + y1) * nhf;
@@ -633,7 +667,7 @@ __device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, 
   }
   float(*P)[N] = PH[b.wave];
   float2* L1[1] = {X[b.wave][grp][0]};
-  fft.template run<+1, 1>(v, L1, q);
+  fft.template run<+1, 1, N == 512>(v, L1, q);
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     P[2 * grp][q + T * m] = v[0][m].x;
@@ -685,7 +719,7 @@ __device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, 
   __syncthreads();
   b.reduce_store(tb, PH, gp, gcg);
   float2* L[2] = {X[b.wave][grp][0], X[b.wave][grp][1]};
-  fft.template run<-1, 2>(w, L, q);
+  fft.template run<-1, 2, N == 512>(w, L, q);
   if (st) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -747,7 +781,7 @@ __device__ __forceinline__ void k_adj_u_body(const int bid, const Tables& tb, fl
     pwy[h] = wyt[ok ? y0 + h : 0];
   }
   float2* L[2] = {X[grp][0], X[grp][1]};
-  fft.template run<+1, 2>(v, L, q);
+  fft.template run<+1, 2, N == 512>(v, L, q);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const float a2y = pa2y[h];
@@ -768,7 +802,7 @@ __device__ __forceinline__ void k_adj_u_body(const int bid, const Tables& tb, fl
         uyr[h][(unsigned)(q + T * m)] = oy[h][m];
       }
   }
-  fft.template run<-1, 2>(v, L, q);
+  fft.template run<-1, 2, N == 512>(v, L, q);
   if (ok) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -812,7 +846,7 @@ __device__ __forceinline__ void k_adj_final_body(const int bid, const Tables& tb
   }
   float(*P)[N] = PH[b.wave];
   float2* L1[1] = {X[b.wave][grp]};
-  fft.template run<+1, 1>(v, L1, q);
+  fft.template run<+1, 1, N == 512>(v, L1, q);
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     P[2 * grp][q + T * m] = v[0][m].x;
