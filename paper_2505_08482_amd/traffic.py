@@ -79,8 +79,9 @@ def main(argv=None) -> int:
     scale = {}
     for counter, expect in (("FETCH_SIZE", COPY_KIB), ("WRITE_SIZE", COPY_KIB)):
         runs = counter_run(counter, COPY, a.work, "copy")
-        # the copy's kernel: the dispatch whose reading is the largest
-        name, (n, val) = max(runs.items(), key=lambda kv: kv[1][1])
+        # the copy's kernel (the fill that makes the source writes the same 1 GiB)
+        copies = {k: v for k, v in runs.items() if "copy" in k.lower()} or runs
+        name, (n, val) = max(copies.items(), key=lambda kv: kv[1][1])
         scale[counter] = expect / val
         print(f"[traffic] calibration {counter}: {name} x{n}, {val:.1f} KiB -> scale {scale[counter]:.4f}",
               flush=True)
