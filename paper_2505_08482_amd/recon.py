@@ -420,6 +420,22 @@ def save_state(path: str, level: int, iters_done: int, prob: Problem, levels_n: 
     os.replace(tmp, path)
 
 
+def _truth_at(c_true, wl: I.Workload, levels: List[I.Workload]) -> torch.Tensor:
+    """The true sound speed on level ``wl``: a callable's value there, or a
+    tensor covering the finest level's physical extent (on that level's grid or
+    a finer one), resampled at the same physical positions."""
+    if callable(c_true):
+        return c_true(wl)
+    g = wl.grid
+    if c_true.shape[-1] == g.nx and c_true.shape[-2] == g.ny:
+        return c_true
+    fg = levels[-1].grid
+    dx_t = fg.dx * fg.nx / c_true.shape[-1]       # the tensor's spacing over the finest level's extent
+    out = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=c_true.device)
+    pat.prolong_phys(c_true.reshape(1, *c_true.shape).contiguous(), dx_t, out, g.dx)
+    return out[0]
+
+
 def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w: torch.Tensor, c_true_fine,
               c_lo: float = 1400.0, c_hi: float = 1600.0, iters: int = 40, memory: int = 20,
               ckpt_every: int = 0, target_Ec: Optional[float] = None, log: Optional[Callable] = None,
@@ -427,8 +443,9 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
               log_path: Optional[str] = None, save_path: Optional[str] = None, save_every: int = 10,
               resume: Optional[str] = None):
     """Coarse-to-fine reconstruction (Sec. 3.1).  ``c_true_fine`` only measures
-    E_c and never enters the optimisation: a tensor on the finest grid
-    (resampled to coarser levels), or a callable ``level workload -> tensor``.
+    E_c and never enters the optimisation: a tensor over the finest level's
+    physical extent (on its grid or a finer one; resampled to each level), or a
+    callable ``level workload -> tensor``.
     Levels may differ in physical extent (Table 1); the converged iterate is
     carried to the next level at the same physical positions.  ``c_init``: the
     starting sound speed inside the mask (default: the middle of the bounds);
@@ -489,15 +506,7 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
                 prev.close()
             z0 = torch.empty_like(x0)
             pat.mul(x0, prob.inv_scale, z0)
-            if callable(c_true_fine):
-                ct = c_true_fine(wl)
-            else:
-                ct = c_true_fine
-                if ct.shape[-1] != g.nx:
-                    fg = levels[-1].grid
-                    ctf = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=device)
-                    pat.prolong_phys(c_true_fine.reshape(1, *c_true_fine.shape).contiguous(), fg.dx, ctf, g.dx)
-                    ct = ctf[0]
+            ct = _truth_at(c_true_fine, wl, levels)
             Ec = []
             Ts = []
             figures = {}
@@ -535,7 +544,7 @@ def multigrid(levels: List[I.Workload], y_fine: torch.Tensor, dt_fine: float, w:
     x = torch.empty_like(z_prev)
     pat.mul(z_prev, prev.scale, x)
     p0, c = prev.split(x)
-    ct = c_true_fine(levels[-1]) if callable(c_true_fine) else c_true_fine
+    ct = _truth_at(c_true_fine, levels[-1], levels)
     out = {"levels": results, "p0": p0.clone(), "c": c.clone(), "seconds": time.perf_counter() - t_all,
            "E_c": relative_error_c(prev, z_prev, ct)}
     prev.close()
