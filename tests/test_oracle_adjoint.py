@@ -115,3 +115,39 @@ def test_finite_differences_every_pixel_32x32():
     ep = np.linalg.norm(fd_p - gp0.ravel()) / np.linalg.norm(gp0)
     assert ec < 1e-6, ec
     assert ep < 1e-6, ep
+
+
+def test_finite_differences_600_steps_sampled_pixels():
+    """The same check over 600 time steps (PML on): central differences of J at
+    96 seeded pixels of c and of p0 (with the PML cells and the corners among
+    them) against the adjoint gradient, per pixel relative to the largest
+    gradient entry."""
+    n, nt, m = 32, 600, 12
+    g, rng, c, p0, xy = _setup(n=n, nt=nt, K=1, m=m, seed=4)
+    y = rng.standard_normal((1, nt, m)) * 0.05
+    w = 3.0
+    data, hist = kspace.forward(g, xy, c, p0)
+    r, J = kspace.misfit(data, y, np.array([w]))
+    gp0, gc = kspace.adjoint_gradient(g, xy, c, p0, r, hist)
+    N = n * n
+    pick = np.unique(np.concatenate([[0, n - 1, N - n, N - 1, 2 * n + 1, n * n // 2 + n // 2],
+                                     np.random.default_rng(40).choice(N, 90, replace=False)]))
+    old = kspace.WORKERS
+    kspace.WORKERS = os.cpu_count() or 1
+    try:
+        ops = kspace.Operators(g)
+        e = np.zeros((len(pick), n, n))
+        e.reshape(len(pick), N)[np.arange(len(pick)), pick] = 1.0
+        hc, hp = 1e-3, 1e-4
+        pr = np.broadcast_to(p0, e.shape)
+        cb = np.broadcast_to(c, e.shape)
+        fd_c = (kspace.objective_batch(g, xy, c[None] + hc * e, pr, y[0], w, ops)
+                - kspace.objective_batch(g, xy, c[None] - hc * e, pr, y[0], w, ops)) / (2 * hc)
+        fd_p = (kspace.objective_batch(g, xy, cb, p0 + hp * e, y[0], w, ops)
+                - kspace.objective_batch(g, xy, cb, p0 - hp * e, y[0], w, ops)) / (2 * hp)
+    finally:
+        kspace.WORKERS = old
+    ec = np.max(np.abs(fd_c - gc.ravel()[pick])) / np.max(np.abs(gc))
+    ep = np.max(np.abs(fd_p - gp0.ravel()[pick])) / np.max(np.abs(gp0))
+    assert ec < 1e-6, ec
+    assert ep < 1e-6, ep
