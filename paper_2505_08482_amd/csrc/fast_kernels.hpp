@@ -353,12 +353,12 @@ __device__ __forceinline__ void k_fwd_u_body(const int bid, const Tables& tb, fl
     uxr[h] = ux + f;
     uyr[h] = uy + f;
     pack_row<N>(v[h], SA + ((size_t)k * ny + y) * nhf, SB + ((size_t)k * ny + y) * nhf, q);
-    if (!first) {
+    // loaded at every step (step 0 ignores them): a load under the step test
+    // would wait for the step counter before it could issue
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        ox[h][m] = uxr[h][(unsigned)(q + T * m)];
-        oy[h][m] = uyr[h][(unsigned)(q + T * m)];
-      }
+    for (int m = 0; m < 8; ++m) {
+      ox[h][m] = uxr[h][(unsigned)(q + T * m)];
+      oy[h][m] = uyr[h][(unsigned)(q + T * m)];
     }
   }
   // PML factors (prefetched before the transforms)
@@ -460,7 +460,7 @@ __device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, 
   // sensor taps of this block's rows (one entry per thread, prefetched)
   const int g0 = tb.g_row_start[ybase], g1 = tb.g_row_start[min(ybase + RC::ROWS, ny)];
   GatherEnt ge{};
-  const bool has_g = dpart_n && (g0 + tid < g1);
+  const bool has_g = dpart && (g0 + tid < g1);   // the argument, not the step-dependent row: no wait for the counter
   if (has_g) ge = tb.g_ent[g0 + tid];
   float2* L[2] = {X[grp][0], X[grp][1]};
   fft.template run<+1, 2, N == 512>(v, L, q);
@@ -624,14 +624,12 @@ __device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, 
     const size_t f = ((size_t)k * ny + y) * N;
     rxr[h] = rhx + f;
     ryr[h] = rhy + f;
-    const float* pr = p_n + f;
     const float* cr = c + (size_t)y * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const unsigned x = q + T * m;
       orx[h][m] = rxr[h][x];
       ory[h][m] = ryr[h][x];
-      op[h][m] = pr[x];
       oc[h][m] = cr[x];
     }
   }
@@ -646,6 +644,15 @@ __device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, 
   for (int h = 0; h < 2; ++h) {
     pay[h] = tb.ay[ok ? y0 + h : 0];
     pay2[h] = tb.ay2[ok ? y0 + h : 0];
+  }
+  // the history slice of step n last: its address waits for the step counter,
+  // and every load above is in flight meanwhile
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int y = ok ? y0 + h : 0;
+    const float* pr = p_n + ((size_t)k * ny + y) * N;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) op[h][m] = pr[(unsigned)(q + T * m)];
   }
   // sensor injections of this block's rows for this wave's dataset: one pixel per lane (prefetched)
   const float* rk = resid_n + (size_t)k * tb.nt * tb.m;
