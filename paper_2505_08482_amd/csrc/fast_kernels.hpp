@@ -71,8 +71,18 @@ template <int N, int TC> struct LdsCol {
 // conflict in every 16-lane group of every read).
 __device__ __forceinline__ int swz_key(int b) { return (b & 7) | ((b & 4) << 1); }
 
-// One register-resident Stockham stage on NV transforms at once (shared barriers).
-template <int N, int T, int R, int NS, int DIR, bool LAST, int NV, bool SWZ = false>
+// Orders one wave's shared-memory writes before its own later reads (a wave
+// executes its shared-memory operations in order; the fences keep the compiler
+// from moving them across), for transforms whose exchanges stay inside a wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One register-resident Stockham stage on NV transforms at once (shared barriers;
+// WAVE: the transform's lanes are one wave, which orders its own exchanges).
+template <int N, int T, int R, int NS, int DIR, bool LAST, int NV, bool SWZ = false, bool WAVE = false>
 __device__ __forceinline__ void rstage(float2 (*v)[8], const float2* w, float2* const* lds, int q) {
   constexpr int B = 8 / R;
   float2 y[NV][B][R];
@@ -114,7 +124,7 @@ __device__ __forceinline__ void rstage(float2 (*v)[8], const float2* w, float2* 
   static_assert(NS % 8 == 0 || (NS == 1 && R == 8), "padded stage offsets");
   static_assert(!SWZ || LAST || (T == 64 && R == 8 && (NS == 1 || NS == 8)), "swizzled stages: 512-point rows");
   constexpr int WSTEP = NS % 8 == 0 ? NS + NS / 8 : 1;
-  __syncthreads();
+  if (WAVE) wave_sync(); else __syncthreads();
   if (SWZ) {
     // stage 1: 8 q + r -> ((8 q) ^ (key & 8)) + (r ^ (key & 7)), key of run q/2;
     // stage 2: base + 8 r (base = 64 (q/8) + q%8) -> (base + 8 r) ^ (12 h + r/2), h = bit 3 of q
@@ -138,7 +148,7 @@ __device__ __forceinline__ void rstage(float2 (*v)[8], const float2* w, float2* 
         for (int r = 0; r < R; ++r) lds[t][pb + r * WSTEP] = y[t][b][r];
     }
   }
-  __syncthreads();
+  if (WAVE) wave_sync(); else __syncthreads();
   if (SWZ) {
     // q + 64 m -> 64 m + (q ^ (q/16 + 12 (m & 1)))
     const int r0 = q ^ (q >> 4), r1 = q ^ ((q >> 4) + 12);
@@ -173,12 +183,13 @@ template <int N, int R1, int R2, int R3> struct RegFft<N, RList<R1, R2, R3>> {
       for (int r = 1; r < R3; ++r) w3[b * (R3 - 1) + r - 1] =
             *at_byte(tw, (unsigned)((r * ((q + T * b) % NS3)) * (N / (NS3 * R3))) * 8u);
   }
-  // SWZ: swizzled shared-memory positions (512-point rows, see swz_key)
-  template <int DIR, int NV, bool SWZ = false>
+  // SWZ: swizzled shared-memory positions (512-point rows, see swz_key);
+  // WAVE: wave-level ordering of the exchanges (every lane of a transform in one wave)
+  template <int DIR, int NV, bool SWZ = false, bool WAVE = false>
   __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
-    rstage<N, T, R1, 1, DIR, false, NV, SWZ>(v, nullptr, lds, q);
-    rstage<N, T, R2, NS2, DIR, false, NV, SWZ>(v, w2, lds, q);
-    rstage<N, T, R3, NS3, DIR, true, NV, SWZ>(v, w3, lds, q);
+    rstage<N, T, R1, 1, DIR, false, NV, SWZ, WAVE>(v, nullptr, lds, q);
+    rstage<N, T, R2, NS2, DIR, false, NV, SWZ, WAVE>(v, w2, lds, q);
+    rstage<N, T, R3, NS3, DIR, true, NV, SWZ, WAVE>(v, w3, lds, q);
   }
 };
 
@@ -192,11 +203,11 @@ template <int N, int R1, int R2> struct RegFft<N, RList<R1, R2>> {
       for (int r = 1; r < R2; ++r) w2[b * (R2 - 1) + r - 1] =
             *at_byte(tw, (unsigned)((r * ((q + T * b) % NS2)) * (N / (NS2 * R2))) * 8u);
   }
-  template <int DIR, int NV, bool SWZ = false>
+  template <int DIR, int NV, bool SWZ = false, bool WAVE = false>
   __device__ __forceinline__ void run(float2 (*v)[8], float2* const* lds, int q) const {
     static_assert(!SWZ, "swizzled stages: 512-point rows only");
-    rstage<N, T, R1, 1, DIR, false, NV>(v, nullptr, lds, q);
-    rstage<N, T, R2, NS2, DIR, true, NV>(v, w2, lds, q);
+    rstage<N, T, R1, 1, DIR, false, NV, false, WAVE>(v, nullptr, lds, q);
+    rstage<N, T, R2, NS2, DIR, true, NV, false, WAVE>(v, w2, lds, q);
   }
 };
 
@@ -271,6 +282,8 @@ template <int N> struct RowF {
   static constexpr int ROWS = 2 * G;
 };
 
+// Row passes run one wave per block (64 threads: RowF<N>::G transforms of
+// two rows each), so their exchanges need wave-level ordering only.
 #define PAT_ROW_PROLOGUE(N)                                                    \
   using RC = RowF<N>;                                                          \
   constexpr int T = RC::T;                                                     \
@@ -368,7 +381,7 @@ __device__ __forceinline__ void k_fwd_u_body(const int bid, const Tables& tb, fl
   pay[0] = tb.asy[ok ? y0 : 0];
   pay[1] = tb.asy[ok ? y1 : 0];
   float2* L[2] = {X[grp][0], X[grp][1]};
-  fft.template run<+1, 2, N == 512>(v, L, q);
+  fft.template run<+1, 2, N == 512, true>(v, L, q);
   // step 0 starts from u^{-1/2} = G/2 (a uniform branch, not a per-element select)
   auto update = [&](auto first_c) {
     constexpr bool F0 = decltype(first_c)::value;
@@ -398,7 +411,7 @@ __device__ __forceinline__ void k_fwd_u_body(const int bid, const Tables& tb, fl
         uyr[h][(unsigned)(q + T * m)] = v[h][m].y;
       }
   }
-  fft.template run<-1, 2, N == 512>(v, L, q);
+  fft.template run<-1, 2, N == 512, true>(v, L, q);
   if (ok) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -463,7 +476,7 @@ __device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, 
   const bool has_g = dpart && (g0 + tid < g1);   // the argument, not the step-dependent row: no wait for the counter
   if (has_g) ge = tb.g_ent[g0 + tid];
   float2* L[2] = {X[grp][0], X[grp][1]};
-  fft.template run<+1, 2, N == 512>(v, L, q);
+  fft.template run<+1, 2, N == 512, true>(v, L, q);
   float2 z[1][8];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -503,7 +516,7 @@ __device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, 
 #pragma unroll
       for (int m = 0; m < 8; ++m) P[2 * grp + h][q + T * m] = 0.f;
   }
-  __syncthreads();
+  wave_sync();   // one-wave blocks
   if (dpart_n) {
     float* dk = dpart_n + (size_t)k * tb.nt * 2 * tb.m;
     if (has_g) {
@@ -517,7 +530,7 @@ __device__ __forceinline__ void k_fwd_rho_body(const int bid, const Tables& tb, 
     }
   }
   float2* L1[1] = {X[grp][0]};
-  fft.template run<-1, 1, N == 512>(z, L1, q);
+  fft.template run<-1, 1, N == 512, true>(z, L1, q);
   if (ok) {
     float2* ra = SA + ((size_t)k * ny + y0) * nhf;
     float2* rb = SA + ((size_t)k * ny + y1) * nhf;
@@ -674,13 +687,14 @@ __device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, 
   }
   float(*P)[N] = PH[b.wave];
   float2* L1[1] = {X[b.wave][grp][0]};
-  fft.template run<+1, 1, N == 512>(v, L1, q);
+  fft.template run<+1, 1, N == 512, true>(v, L1, q);   // each wave's own rows
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     P[2 * grp][q + T * m] = v[0][m].x;
     P[2 * grp + 1][q + T * m] = v[0][m].y;
   }
-  __syncthreads();
+  // the wave's own rows (P = PH[wave]): wave-level ordering suffices until the group sum
+  wave_sync();
   if (inj_at >= 0) (&P[0][0])[inj_at] += inj;
   if (e1 - e0 > 64) {   // rows crowded with sensors: the remaining pixels, one pass each
     for (int e2 = e0 + 64 + lane; e2 < e1; e2 += 64) {
@@ -693,7 +707,7 @@ __device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, 
       (&P[0][0])[(px.row - ybase) * N + px.ix] += acc;
     }
   }
-  __syncthreads();
+  wave_sync();
   float2 w[2][8];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -726,7 +740,7 @@ __device__ __forceinline__ void k_adj_rho_body(const int bid, const Tables& tb, 
   __syncthreads();
   b.reduce_store(tb, PH, gp, gcg);
   float2* L[2] = {X[b.wave][grp][0], X[b.wave][grp][1]};
-  fft.template run<-1, 2, N == 512>(w, L, q);
+  fft.template run<-1, 2, N == 512, true>(w, L, q);
   if (st) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -788,7 +802,7 @@ __device__ __forceinline__ void k_adj_u_body(const int bid, const Tables& tb, fl
     pwy[h] = wyt[ok ? y0 + h : 0];
   }
   float2* L[2] = {X[grp][0], X[grp][1]};
-  fft.template run<+1, 2, N == 512>(v, L, q);
+  fft.template run<+1, 2, N == 512, true>(v, L, q);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const float a2y = pa2y[h];
@@ -809,7 +823,7 @@ __device__ __forceinline__ void k_adj_u_body(const int bid, const Tables& tb, fl
         uyr[h][(unsigned)(q + T * m)] = oy[h][m];
       }
   }
-  fft.template run<-1, 2, N == 512>(v, L, q);
+  fft.template run<-1, 2, N == 512, true>(v, L, q);
   if (ok) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
