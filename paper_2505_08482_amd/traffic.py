@@ -26,6 +26,7 @@ import os
 import re
 import subprocess
 import sys
+import tempfile
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -69,7 +70,8 @@ def counter_run(counter: str, cmd, work: str, tag: str):
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--work", default=os.path.join(ROOT, "gpurun_out", "traffic"))
+    ap.add_argument("--work", default=os.path.join(tempfile.gettempdir(), "pat_traffic"),
+                    help="folder for the counter runs' raw output")
     ap.add_argument("--out", default=OUT)
     a = ap.parse_args(argv)
     os.makedirs(a.work, exist_ok=True)
