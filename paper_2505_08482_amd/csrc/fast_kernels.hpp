@@ -948,7 +948,6 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
   float2* const colB = SB + (size_t)k * N * nhf;
   const unsigned lane_b = ((unsigned)q * nhf + (ok ? cx : 0)) * 8u, row_b = (unsigned)T * nhf * 8u;
   Fft<N> fft;
-  fft.init(tb.tw_y, q);
   float2 a[2][8];
   if (SEQ) {
 #pragma unroll
@@ -975,6 +974,17 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
   const float2* eyt = PLUS ? tb.ey_p : tb.ey_m;
   const float2* ext = PLUS ? tb.ex_p : tb.ex_m;
   const bool col0 = c0 == 0 && cl == 0;   // DC + i Nyquist column
+  // the tables every column of the block shares (transform twiddles, y shift
+  // factors) pass through shared memory: a few loads per thread instead of
+  // one per twiddle and factor
+  constexpr int NTH = TC * T, NST = (N + NTH - 1) / NTH;
+  __shared__ float2 TWs[N], EYs[N];
+  float2 stw[NST], sey[NST];
+#pragma unroll
+  for (int j = 0; j < NST; ++j) {
+    const int i = tid + j * NTH;
+    if (NTH * NST == N || i < N) { stw[j] = tb.tw_y[i]; sey[j] = eyt[i]; }
+  }
   float kap[8], kapN[8];
   float2 eyv[8];
   const float2 exv = ext[col0 ? 0 : (ok ? cx : 0)];
@@ -985,15 +995,20 @@ __device__ __forceinline__ void k_col_body(const int bid, const Tables& tb, floa
   const float* const kcol = tb.kappa + (size_t)(ok ? cx : 0) * N;
   const float* const kcolN = tb.kappa + (size_t)(nx / 2) * N;
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int e = q + T * m;
-    kap[m] = kcol[e] * scale;
-    eyv[m] = eyt[e];
-  }
+  for (int m = 0; m < 8; ++m) kap[m] = kcol[q + T * m] * scale;
   if (c0 == 0) {
 #pragma unroll
     for (int m = 0; m < 8; ++m) kapN[m] = kcolN[q + T * m] * scale;
   }
+#pragma unroll
+  for (int j = 0; j < NST; ++j) {
+    const int i = tid + j * NTH;
+    if (NTH * NST == N || i < N) { TWs[i] = stw[j]; EYs[i] = sey[j]; }
+  }
+  __syncthreads();
+  fft.init(TWs, q);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) eyv[m] = EYs[q + T * m];
   float2* LL[2] = {LA + cl * P, LB + cl * P};
   if (TWO_IN && SEQ) {
     fft.template run<-1, 1>(&a[0], &LL[0], q);
