@@ -56,6 +56,12 @@ def counter_run(counter: str, cmd, work: str, tag: str):
     print("[traffic] " + " ".join(full), flush=True)
     with open(d + ".log", "w") as log:
         subprocess.run(full, check=True, stdout=log, stderr=subprocess.STDOUT, cwd=ROOT)
+    return read_counter(d, counter)
+
+
+def read_counter(d: str, counter: str):
+    """Per-kernel (dispatch count, mean reading) of ``counter`` in the
+    rocprofv3 counter-collection CSV files under folder ``d``."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise RuntimeError(f"no counter file under {d}")
@@ -66,6 +72,22 @@ def counter_run(counter: str, cmd, work: str, tag: str):
                 if r["Counter_Name"] == counter:
                     acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+
+
+def pass_readings(fetch, write):
+    """The fused passes' readings (kernel name, dispatches, mean FETCH_SIZE
+    and WRITE_SIZE in KiB) from the per-kernel results of the two runs."""
+    passes = {}
+    for pattern, kind in PASS_OF:
+        for kname, (n, f) in fetch.items():
+            if re.search(pattern, kname) and kname in write:
+                passes[kind] = {"kernel": kname.split("(")[0], "dispatches": n, "fetch_kib": round(f, 1),
+                                "write_kib": round(write[kname][1], 1)}
+                break
+    missing = [k for _, k in PASS_OF if k not in passes]
+    if missing:
+        raise RuntimeError(f"pass kernels not found in the counter runs: {missing}")
+    return passes
 
 
 def main(argv=None) -> int:
@@ -88,16 +110,7 @@ def main(argv=None) -> int:
         print(f"[traffic] calibration {counter}: {name} x{n}, {val:.1f} KiB -> scale {scale[counter]:.4f}",
               flush=True)
     readings = {c: counter_run(c, BENCH, a.work, "bench") for c in ("FETCH_SIZE", "WRITE_SIZE")}
-    passes = {}
-    for pattern, kind in PASS_OF:
-        for kname, (n, fetch) in readings["FETCH_SIZE"].items():
-            if re.search(pattern, kname) and kname in readings["WRITE_SIZE"]:
-                passes[kind] = {"kernel": kname.split("(")[0], "dispatches": n, "fetch_kib": round(fetch, 1),
-                                "write_kib": round(readings["WRITE_SIZE"][kname][1], 1)}
-                break
-    missing = [k for _, k in PASS_OF if k not in passes]
-    if missing:
-        raise RuntimeError(f"pass kernels not found in the counter runs: {missing}")
+    passes = pass_readings(readings["FETCH_SIZE"], readings["WRITE_SIZE"])
     out = {"workload": WORKLOAD, "source_sha256": bench.kernel_source_digest(),
            "fetch_scale": round(scale["FETCH_SIZE"], 4), "write_scale": round(scale["WRITE_SIZE"], 4),
            "calibration": "device copy of 2^28 float32 (1 GiB read, 1 GiB written), largest dispatch",
