@@ -39,6 +39,57 @@ static void plan_case(const char* what, int nx, int ny, int K, int m, double rad
   free(xy);
 }
 
+/* deterministic generator for the sweep below (64-bit LCG, top 53 bits) */
+static unsigned long long lcg_state = 0x2505084820250508ULL;
+static double uniform(void) {
+  lcg_state = lcg_state * 6364136223846793005ULL + 1442695040888963407ULL;
+  return (double)(lcg_state >> 11) * (1.0 / 9007199254740992.0);
+}
+static int pick(int n) { return (int)(uniform() * n) % n; }
+
+/* Random plans over every supported axis length (square and not), dataset
+ * count, PML width and sensor set, sensors anywhere their four bilinear taps
+ * stay on the grid (fractional cell-centre index in [0, n - 1), kept 1e-6
+ * cells from both ends so that rounding of the position cannot decide); every
+ * fourth plan on a grid whose spacing is a power of two, where the position
+ * arithmetic is exact, with one sensor on the first cell centre (index 0,
+ * inside).  Then the same sets with one sensor 1e-6 cells beyond either end
+ * of either axis's range. */
+static void random_plans(int want_ok) {
+  static const int len[] = {32, 36, 40, 48, 64, 81, 84, 96, 125, 128, 160, 175, 192, 243, 256, 375, 384, 512, 768};
+  const int nlen = (int)(sizeof len / sizeof len[0]);
+  char what[160];
+  for (int t = 0; t < 48; ++t) {
+    const int nx = len[t < nlen ? t : pick(nlen)], ny = t < nlen ? nx : len[pick(nlen)];
+    const int K = 1 + pick(64), m = 1 + pick(2500);
+    const int pml = pick((nx < ny ? nx : ny) / 2);
+    const double dx = t % 4 == 0 ? 1.0 / 8192.0 : 1e-4;
+    pat_grid g = {nx, ny, 20, pml, dx, 1.875e-8, 1600.0, 1000.0, 2.0};
+    double* xy = (double*)malloc(sizeof(double) * 2 * (size_t)m);
+    for (int s = 0; s < m; ++s) {
+      /* fractional cell-centre index f in [0, n - 1): position (f + 0.5 - n/2) dx */
+      const double fx = 1e-6 + uniform() * (nx - 1 - 2e-6), fy = 1e-6 + uniform() * (ny - 1 - 2e-6);
+      xy[2 * s] = (fx + 0.5 - nx / 2.0) * dx;
+      xy[2 * s + 1] = (fy + 0.5 - ny / 2.0) * dx;
+    }
+    if (t % 4 == 0) { xy[0] = (0.5 - nx / 2.0) * dx; xy[1] = (0.5 - ny / 2.0) * dx; }   /* first cell centre, exact */
+    pat_plan* p = NULL;
+    snprintf(what, sizeof what, "random plan %d: %dx%d K %d m %d pml %d", t, nx, ny, K, m, pml);
+    const int st = pat_plan_create(&g, K, m, xy, &p);
+    expect(what, st, want_ok);
+    if (st == PAT_OK) pat_plan_destroy(p);
+    /* one sensor just outside, 1e-6 cells before index 0 or beyond index n - 1, on either axis */
+    const int s = pick(m), side = pick(4);
+    const double out_f[4] = {-1e-6, nx - 1 + 1e-6, -1e-6, ny - 1 + 1e-6};
+    if (side < 2) xy[2 * s] = (out_f[side] + 0.5 - nx / 2.0) * dx;
+    else xy[2 * s + 1] = (out_f[side] + 0.5 - ny / 2.0) * dx;
+    snprintf(what, sizeof what, "random plan %d, sensor %d outside (side %d)", t, s, side);
+    p = NULL;
+    expect(what, pat_plan_create(&g, K, m, xy, &p), PAT_EINVAL);
+    free(xy);
+  }
+}
+
 int main(void) {
   /* valid plans: on a machine without a GPU the table upload fails (PAT_EHIP)
    * after every host table has been built */
@@ -57,6 +108,7 @@ int main(void) {
     pat_plan* p = NULL;
     expect("pixel centres and edges", pat_plan_create(&g, 2, 4, xy, &p), want_ok);
   }
+  random_plans(want_ok);
   /* invalid plans */
   plan_case("sensor outside the grid", 64, 64, 1, 8, 40.0, 8, PAT_EINVAL);
   plan_case("unsupported length", 100, 100, 1, 8, 20.0, 8, PAT_EUNSUPPORTED);

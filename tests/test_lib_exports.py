@@ -100,3 +100,36 @@ def test_nn_host_side_argument_checks():
                                None) == pat.PAT_EINVAL                                   # transpose of a non-square
     assert L.pat_nn_pack_input(8, 8, 1, d16, d16, None, 0, 1500.0, 100.0, d16, d16, d16, d16, 1 << 12,
                                None) == pat.PAT_EINVAL                                   # target without c_true
+
+
+@pytest.mark.skipif(not os.path.exists(pat.LIB_PATH), reason="libpat.so not built")
+def test_library_and_oracle_accept_the_same_sensor_positions():
+    """A sensor is accepted where its four bilinear taps lie on the grid
+    (fractional cell-centre index in [0, n - 1) on each axis), by the library
+    and by the oracle alike; the spacing is a power of two, so the positions
+    are exact.  Without a GPU an accepted plan fails at its first device
+    allocation (PAT_EHIP), after every host table has been built."""
+    import numpy as np
+    from oracle import sensors as osens
+    L = pat.lib()
+    nx, ny, dx = 64, 48, 1.0 / 8192
+    g = pat.pat_grid(nx, ny, 10, 4, dx, 1e-8, 1600.0, 1000.0, 2.0)
+    fx_cases = [0.0, 1e-9, 31.5, nx - 1 - 1e-9, nx - 1.0, -1e-9, nx + 3.0]
+    fy_cases = [0.0, ny - 1 - 1e-9, ny - 1.0, -1e-9]
+    for fx in fx_cases:
+        for fy in fy_cases:
+            x, y = (fx + 0.5 - nx / 2) * dx, (fy + 0.5 - ny / 2) * dx
+            xy = (ctypes.c_double * 2)(x, y)
+            h = ctypes.c_void_p()
+            st = L.pat_plan_create(ctypes.byref(g), 1, 1, xy, ctypes.byref(h))
+            if st == pat.PAT_OK:
+                L.pat_plan_destroy(h)
+            assert st in (pat.PAT_OK, pat.PAT_EHIP, pat.PAT_EINVAL), st
+            try:
+                osens.sensor_matrix(nx, ny, dx, np.array([[x, y]]))
+                oracle_ok = True
+            except ValueError:
+                oracle_ok = False
+            inside = 0 <= fx < nx - 1 and 0 <= fy < ny - 1
+            assert oracle_ok == inside, (fx, fy)
+            assert (st != pat.PAT_EINVAL) == inside, (fx, fy, st)
