@@ -73,6 +73,10 @@ typedef struct pat_plan pat_plan;
  * positions `sensor_xy` (HOST, [m][2] metres, (x, y), origin at the grid
  * centre).  Sec. 2.2: the pressure at a sensor is the bilinear interpolation
  * of its four surrounding pixels; the adjoint injects with the transpose.
+ * Pixel i of an axis with n points is centred at (i + 1/2 - n/2) dx; a sensor
+ * is inside the interpolation range when its fractional pixel index
+ * x / dx + n/2 - 1/2 lies in [0, n - 1) on both axes (the last pixel centre
+ * itself is outside: its upper neighbour would be off the grid).
  * Supported axis lengths: 32 36 40 48 64 81 84 96 125 128 160 175 192 243 256
  * 375 384 512 768 (products of 2, 3, 5, 7 with a compiled radix plan).
  * Errors: PAT_EINVAL (sizes, sensor outside the interpolation range),
